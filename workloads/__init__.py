@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/bench and the oracle.
+
+This module holds no arithmetic of the method itself: it only produces box
+occupancy sets (integer box coordinates), random complex coefficient vectors
+and random per-box basis matrices, all from ``numpy.random.default_rng(seed)``.
+Both sides receive exactly the same arrays; the HIP path gets them rounded to
+complex64 and the oracle gets those rounded values upcast to complex128.
+
+Geometries stand in for the paper's meshes (PEC/dielectric spheres, flamme,
+almond), which are not available: a box grid partition of the mother box
+(Sec. 2, the 8^L child boxes of side ``a``) only needs the set of occupied
+child boxes, which these generators produce directly.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Workload",
+    "grid_boxes",
+    "shell_boxes",
+    "plate_boxes",
+    "mask_boxes",
+    "complex_normal",
+    "random_basis",
+    "config",
+    "CONFIGS",
+]
+
+
+def grid_boxes(nx: int, ny: int, nz: int) -> np.ndarray:
+    """All boxes of an ``nx x ny x nz`` grid, as an (n, 3) int32 array.
+
+    Order: x slowest, z fastest (lexicographic), which is also the order the
+    oracle and the library use to number boxes.
+    """
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz),
+                             indexing="ij"), axis=-1)
+    return g.reshape(-1, 3).astype(np.int32)
+
+
+def shell_boxes(radius: float, thickness: float, a: float) -> np.ndarray:
+    """Boxes of side ``a`` whose centre lies in the spherical shell
+    ``radius - thickness/2 <= |r| < radius + thickness/2``.
+
+    The sphere is centred on the centre of the middle box of a cubic grid of
+    ``2*ceil((radius + thickness/2)/a) + 1`` boxes per side, so box ``c`` has
+    its centre at ``a*(c - m)`` relative to the sphere centre, ``m`` being the
+    middle index. All lengths are in the same unit (wavelengths here).
+    The integer test |d|^2 in [lo^2, hi^2) is exact for the half-integer
+    radii used by the shipped workloads.
+    """
+    half = int(math.ceil((radius + thickness / 2) / a))
+    n = 2 * half + 1
+    c = grid_boxes(n, n, n)
+    d = (c - half).astype(np.float64) * a
+    r = np.sqrt((d * d).sum(axis=1))
+    keep = (r >= radius - thickness / 2) & (r < radius + thickness / 2)
+    return c[keep]
+
+
+def plate_boxes(lx: float, ly: float, lz: float, a: float) -> np.ndarray:
+    """A solid ``lx x ly x lz`` plate voxelised into boxes of side ``a``."""
+    n = [max(1, int(round(v / a))) for v in (lx, ly, lz)]
+    return grid_boxes(*n)
+
+
+def mask_boxes(n_target: int, rho: float, seed: int) -> np.ndarray:
+    """Bernoulli(rho) occupancy of a cube of side ``ceil((n_target/rho)^(1/3))``.
+
+    At least one box is always kept so the set is never empty.
+    """
+    rng = np.random.default_rng(seed)
+    side = max(1, int(math.ceil((n_target / rho) ** (1.0 / 3.0))))
+    c = grid_boxes(side, side, side)
+    keep = rng.random(len(c)) < rho
+    if not keep.any():
+        keep[rng.integers(len(c))] = True
+    return c[keep]
+
+
+def complex_normal(shape, seed: int, dtype=np.complex64) -> np.ndarray:
+    """i.i.d. N(0,1) real and imaginary parts."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    return z.astype(dtype)
+
+
+def random_basis(nb: np.ndarray, n_u: int, seed: int,
+                 dtype=np.complex64) -> tuple[np.ndarray, np.ndarray]:
+    """Random per-box basis matrices ``S_i`` (``n_u x nb[i]``, column-major).
+
+    Returns ``(nb_ptr, S)`` where ``nb_ptr`` is the (n_box+1,) int64 prefix
+    sum of ``nb`` and ``S`` is the flat concatenation of the column-major
+    blocks (length ``n_u * nb_ptr[-1]``). Entries are complex N(0,1)/sqrt(n_u)
+    so that ``S_i x_i`` keeps unit scale.
+    """
+    nb = np.asarray(nb, dtype=np.int64)
+    nb_ptr = np.zeros(len(nb) + 1, dtype=np.int64)
+    np.cumsum(nb, out=nb_ptr[1:])
+    total = int(nb_ptr[-1]) * n_u
+    S = complex_normal((total,), seed, np.complex128) / math.sqrt(n_u)
+    return nb_ptr, S.astype(dtype)
+
+
+@dataclass
+class Workload:
+    """One synthetic far-zone MVM problem."""
+
+    name: str
+    boxes: np.ndarray            # (n_box, 3) int32, unique, >= 0
+    a: float                     # box side, wavelengths
+    k: float                     # wavenumber, rad per wavelength
+    n_d: int                     # dipoles per box edge
+    far_mode: str                # "ilist" or "full"
+    nrhs: int = 1
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_box(self) -> int:
+        return int(len(self.boxes))
+
+    @property
+    def n_u(self) -> int:
+        return 3 * self.n_d ** 3
+
+    def coefficients(self, nb_total: int | None = None, seed: int | None = None,
+                     dtype=np.complex64) -> np.ndarray:
+        """``[nrhs][sum N_b]`` coefficient vectors (identity basis: N_b = n_u)."""
+        n = self.n_box * self.n_u if nb_total is None else nb_total
+        return complex_normal((self.nrhs, n), self.seed if seed is None else seed,
+                              dtype)
+
+
+TWO_PI = 2.0 * math.pi
+
+
+def config(idx: int, **over) -> Workload:
+    """The named synthetic workloads.
+
+    1: 6x6x6 full grid, a = 0.25 wavelength, k = 2 pi, n_d = 3, ILIST.
+    2: spherical shell, radius 4, thickness 0.25, a = 0.25 (centre rule).
+    3: the same shell at a = 0.125 (and ``variant="plate"``: a 0.5 x 2 x 8
+       plate at a = 0.125).
+    """
+    if idx == 1:
+        w = Workload("grid6_a0.25", grid_boxes(6, 6, 6), 0.25, TWO_PI, 3,
+                     "ilist", seed=1)
+    elif idx == 2:
+        w = Workload("shell_r4_t0.25_a0.25", shell_boxes(4.0, 0.25, 0.25),
+                     0.25, TWO_PI, 3, "ilist", seed=2)
+    elif idx == 3:
+        if over.pop("variant", "shell") == "plate":
+            w = Workload("plate_0.5x2x8_a0.125",
+                         plate_boxes(0.5, 2.0, 8.0, 0.125), 0.125, TWO_PI, 3,
+                         "ilist", seed=3)
+        else:
+            w = Workload("shell_r4_t0.25_a0.125",
+                         shell_boxes(4.0, 0.25, 0.125), 0.125, TWO_PI, 3,
+                         "ilist", seed=3)
+    else:
+        raise ValueError(f"unknown workload {idx}")
+    for key, v in over.items():
+        setattr(w, key, v)
+    return w
+
+
+CONFIGS = (1, 2, 3)
