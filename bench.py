@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Far-zone MVM throughput on one MI355X.
+
+One step is one far-zone matrix-vector product y = T G S x (aggregation,
+translation over the interaction list, disaggregation) of one right-hand
+side, on the 3,338-box spherical shell (radius 4, thickness 0.25, boxes of
+0.25 wavelength, 3x3x3 dipoles = 81 coefficients per box, 81 synthetic
+basis functions per box), as an iterative solver would issue it. Inputs
+(50 seeded vectors, cycled) and the basis matrices are resident in HBM
+before timing starts; the plan (far set, operator table) is built once.
+
+Prints one JSON line with the throughput, latency percentiles, the
+roofline position of the dominant kernel (timed with HIP events on the
+stream it runs on) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E peak
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--basis", choices=["synthetic", "identity"], default="synthetic")
+    ap.add_argument("--workload", type=int, default=2,
+                    help="synthetic workload index (2 = 3,338-box shell)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="time budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
+    """Time the FP64 oracle on the same workload (bounded sample)."""
+    import numpy as np
+    import oracle as O
+    from threadpoolctl import threadpool_info
+
+    S128 = None if S is None else S.astype(np.complex128)
+    x = x0.astype(np.complex128)
+    t0 = time.perf_counter()
+    n = 0
+    y_ref = None
+    while True:
+        y = O.far_mvm(x, w.boxes, w.a, w.k, w.n_d, nb_ptr, S128, mode=w.far_mode)
+        if y_ref is None:
+            y_ref = y
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()
+                   if p.get("user_api") == "blas"] or [1])
+    rel = float(np.linalg.norm(y0_gpu - y_ref) / np.linalg.norm(y_ref))
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {
+        "value": n / dt, "unit": "MVM/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"{n} full far-zone MVMs of the same workload in {dt:.1f} s "
+                  f"(NumPy FP64, grouped by offset; {len(os.sched_getaffinity(0))} "
+                  f"host cores visible, {cpu_model})",
+    }, rel
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_2501_04684_amd as U
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.config(args.workload)
+    nrhs = args.nrhs
+
+    t0 = time.perf_counter()
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=nrhs)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = ff.info
+
+    nb_ptr = S = None
+    if args.basis == "synthetic":
+        nb = np.full(w.n_box, w.n_u)
+        nb_ptr, S = W.random_basis(nb, w.n_u, seed=w.seed)
+        S_dev = torch.from_numpy(S).to(dev)
+        ff.set_basis(nb_ptr, S_dev)
+    nb_total = ff.nb_total
+    n_vec = 50
+    X = torch.from_numpy(W.complex_normal((n_vec, nrhs, nb_total), seed=1000)).to(dev)
+    Y = torch.empty((nrhs, nb_total), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    for s in range(args.warmup):
+        U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    U.profile_begin(ff.plan, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stage_ms, call_ms = U.profile_end(ff.plan, K)
+
+    # result of the first vector, for the accuracy figure
+    U.far_mvm(ff.plan, X[0], Y, nrhs, stream)
+    torch.cuda.synchronize()
+    y0 = Y.cpu().numpy()
+
+    value = K * nrhs / dt
+    avg_us = stage_ms / K * 1e3
+    n_pairs, n_box, nu = info["n_pairs"], info["n_boxes"], info["n_u"]
+    s_bytes = 0 if S is None else S.nbytes
+    stage_names = ["aggregate", "translate", "disaggregate"]
+    # algorithmic work per launch
+    flops = info["translate_flops"] * nrhs
+    bytes_agg = s_bytes + nrhs * (nb_total + n_box * nu) * 8
+    bytes_dis = s_bytes + nrhs * (n_box * nu + nb_total) * 8
+    dom = int(np.argmax(avg_us))
+    if dom == 1:
+        ach = flops / (avg_us[1] * 1e-6) / 1e12
+        roof = {"kernel": "translate", "bound": "mfma", "achieved": ach,
+                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
+    else:
+        b = bytes_agg if dom == 0 else bytes_dis
+        ach = b / (avg_us[dom] * 1e-6) / 1e9
+        roof = {"kernel": stage_names[dom], "bound": "hbm", "achieved": ach,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                "traffic": None}
+    trans_tflops = flops / (avg_us[1] * 1e-6) / 1e12
+    stages = {
+        name: {"avg_us": float(avg_us[i])} for i, name in enumerate(stage_names)}
+    stages["translate"].update(tflops=trans_tflops,
+                               frac_fp32_mfma=trans_tflops / PEAK_FP32_MFMA_TFLOPS)
+    if S is not None:
+        stages["aggregate"]["gbs"] = bytes_agg / (avg_us[0] * 1e-6) / 1e9
+        stages["disaggregate"]["gbs"] = bytes_dis / (avg_us[2] * 1e-6) / 1e9
+
+    out = {
+        "metric": "far-zone MVMs/s", "value": value, "unit": "MVM/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n_boxes": n_box, "n_pairs": n_pairs,
+                   "n_offsets": info["n_offsets"], "n_u": nu, "far_mode": w.far_mode,
+                   "basis": (f"synthetic, {w.n_u} functions per box"
+                             if S is not None else "identity"),
+                   "nrhs": nrhs},
+        "p50_ms": float(np.percentile(call_ms, 50)),
+        "p99_ms": float(np.percentile(call_ms, 99)),
+        "plan_ms": plan_ms,
+        "stages": stages,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        cb, rel = cpu_baseline(w, nb_ptr, S, X[0].cpu().numpy(), y0, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["rel_l2_vs_oracle"] = rel
+    print(json.dumps(out))
+    ff.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,213 @@
+/*
+ * ubf.h -- far-zone matrix-vector product of the uniform-basis,
+ * group-by-group integral-equation method (arXiv 2501.04684,
+ * Koc, Kalfa, Dogan, Erturk), on one AMD Instinct MI355X (gfx950).
+ *
+ * The product evaluated is y = T * G_far * S * x, the far part Z^F I of
+ * Eq. (2), in three stages (Algorithm 5):
+ *   1. aggregate:    P_i = S_i x_i              (Sec. 2.1, Eq. 11, Algorithm 1)
+ *   2. translate:    E_j = sum_{i in F_j} G_{c_j - c_i} P_i
+ *                                              (Sec. 2.2, Eq. 13-14, Algorithm 2)
+ *   3. disaggregate: y_j = T_j E_j              (Sec. 2.3, Eq. 15-17, Algorithm 3)
+ *
+ * Geometry (Sec. 2, box partition; Sec. 2.2, translation vectors): the
+ * caller gives the integer coordinates c of the occupied child boxes of
+ * side a. Box c has its centre at a*(c + 1/2). Each box carries n_d^3
+ * Hertzian dipoles on a cell-centred uniform lattice, site m in
+ * {0..n_d-1}^3 at a*((m + 1/2)/n_d - 1/2) from the box centre, site index
+ * s = (m_x*n_d + m_y)*n_d + m_z, and three components per site, so
+ * N_u = 3*n_d^3 coefficients per box with index u = 3*s + alpha
+ * (alpha = x, y, z).
+ *
+ * Far set: UBF_FAR_FULL takes every pair with Chebyshev offset >= 2
+ * (Algorithm 2's ||w|| >= 2a on the box lattice); UBF_FAR_ILIST further
+ * keeps only pairs whose parent boxes floor(c/2) are Chebyshev-adjacent
+ * (the one-box-buffer interaction list of a two-level tree; its 316
+ * distinct offsets are the translation vectors counted in Sec. 2.2).
+ *
+ * Operators: G_w[(l,alpha),(s,beta)] = D(a*w + r_l - r_s)[alpha][beta],
+ * D the free-space dyadic Green's function of Eq. (5)-(6) with time
+ * convention exp(+j omega t). They are generated on the host in FP64 at
+ * plan creation and stored once per distinct offset in FP32.
+ *
+ * Conventions shared by every entry point:
+ *   - Status codes: UBF_OK (0) or a negative UBF_E* value. No exception
+ *     crosses this interface and nothing aborts. ubf_last_error() returns
+ *     a thread-local message describing the last failure on this thread.
+ *   - All argument checks finish before any HIP call, so an invalid
+ *     argument never leaves work queued. Errors of kernels already queued
+ *     surface at a later call (as from any asynchronous HIP work).
+ *   - Device memory is owned by the caller. The library never allocates
+ *     device memory; it works in the caller's workspace (ubf_plan_bind).
+ *   - "d_" arguments are device pointers; all others are host pointers.
+ *   - Complex vectors are complex64, interleaved (re, im) float pairs, the
+ *     layout of torch.complex64, laid out [nrhs][length] row-major.
+ *   - hip_stream is a hipStream_t (NULL = the null stream). Compute entry
+ *     points only enqueue work on it and return. A plan may be used by one
+ *     stream at a time: two calls on one plan that overlap in time race on
+ *     its workspace.
+ */
+#ifndef UBF_H
+#define UBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ubf_status {
+  UBF_OK = 0,
+  UBF_EINVAL = -1,   /* invalid argument */
+  UBF_ENOMEM = -2,   /* workspace too small, or a host allocation failed */
+  UBF_EDEVICE = -3,  /* a HIP runtime call failed */
+  UBF_ESTATE = -4    /* plan not bound to a workspace / wrong state */
+};
+
+enum ubf_far_mode {
+  UBF_FAR_ILIST = 0, /* parent-adjacent pairs with Chebyshev offset >= 2 */
+  UBF_FAR_FULL = 1   /* every pair with Chebyshev offset >= 2 (Algorithm 2) */
+};
+
+enum ubf_precision {
+  UBF_FP32 = 0       /* FP32 operands, FP32 accumulation */
+};
+
+/* Problem statement (Sec. 2: box grid, dipoles per box, wavenumber). */
+typedef struct ubf_problem {
+  int64_t n_boxes;         /* number of occupied boxes, >= 1 */
+  const int32_t* box_ijk;  /* host, 3*n_boxes: (x, y, z) per box, each >= 0,
+                              no duplicates; copied at creation */
+  double a;                /* box side, > 0 */
+  double k;                /* free-space wavenumber, > 0, per unit of a */
+  double eta;              /* intrinsic impedance; 0 selects 376.730313668 */
+  int32_t n_d;             /* dipoles per box edge, 1..4 */
+  int32_t far_mode;        /* enum ubf_far_mode */
+  int32_t precision;       /* enum ubf_precision */
+} ubf_problem;
+
+/* Sizes and work counts of a plan, for benchmarks and tests. */
+typedef struct ubf_info {
+  int64_t n_boxes;
+  int64_t n_pairs;          /* far-zone (test, source) box pairs */
+  int32_t n_offsets;        /* distinct translation vectors */
+  int32_t n_orbits;         /* classes under the 48 cube symmetries */
+  int32_t n_u;              /* uniform-basis coefficients per box, 3*n_d^3 */
+  int32_t n_d;
+  int64_t n_chunks;         /* translation work units (per RHS) */
+  int64_t table_bytes;      /* device operator table */
+  double translate_flops;   /* real flops per RHS: 8 * n_u^2 * n_pairs */
+  int32_t mfma;             /* 1 if stage 2 runs on the matrix cores */
+  int32_t reserved;
+} ubf_info;
+
+typedef struct ubf_plan ubf_plan;
+
+/* Build a plan on the host (no device work): validate the problem, build
+ * the far set (Algorithm 2), its distinct offsets and their symmetry
+ * orbits (Sec. 2.2), the work partition, and the FP32 operator table
+ * from FP64 evaluations of Eq. (5)-(6) and (13).
+ * Errors: UBF_EINVAL for a null pointer, n_boxes < 1, a negative or
+ * duplicate coordinate, a <= 0, k <= 0, eta < 0, n_d outside 1..4, an
+ * unknown far_mode or precision, or a far set beyond 2^31-1 pairs;
+ * UBF_ENOMEM if host memory runs out. *out is set only on success. */
+int ubf_plan_create(const ubf_problem* problem, ubf_plan** out);
+
+/* Device workspace bytes needed to run up to max_nrhs right-hand sides
+ * per call (operator table, index tables, internal vectors). Returns 0 for
+ * a null plan or max_nrhs < 1. */
+size_t ubf_workspace_bytes(const ubf_plan* plan, int32_t max_nrhs);
+
+/* Attach a caller-owned device workspace of `bytes` bytes (>= the size
+ * ubf_workspace_bytes(plan, max_nrhs) returns; 256-byte aligned) and copy
+ * the plan's tables into it on hip_stream, waiting for the copy to end.
+ * The workspace must stay allocated until the plan is destroyed or bound
+ * again. Errors: UBF_EINVAL (null, misaligned, max_nrhs < 1), UBF_ENOMEM
+ * (too small), UBF_EDEVICE (copy failed). */
+int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
+                  int32_t max_nrhs, void* hip_stream);
+
+/* Set the subdomain basis (Algorithm 1 and 3 preprocessing results).
+ * nb_ptr: host, n_boxes+1 prefix sums of the per-box function counts N_b,i
+ *   (nb_ptr[0] = 0, non-decreasing); copied.
+ * d_S: per box, S_i = A^dagger [B_1..B_Nb] of size N_u x N_b,i, complex64,
+ *   column-major, the boxes' blocks concatenated in box order.
+ * d_T: per box, T_i of size N_b,i x N_u, complex64, column-major,
+ *   concatenated; NULL means T_i = S_i^T (Galerkin point testing).
+ * Passing nb_ptr = NULL and d_S = NULL restores the identity basis, in
+ * which x holds the N_u uniform-basis coefficients of every box.
+ * The matrices stay owned by the caller and must outlive their use.
+ * Needs a bound plan (it copies nb_ptr into the workspace, synchronously).
+ * Errors: UBF_EINVAL (bad prefix sums, d_S NULL with nb_ptr given),
+ * UBF_ESTATE (unbound), UBF_EDEVICE. */
+int ubf_plan_set_basis(ubf_plan* plan, const int64_t* nb_ptr,
+                       const void* d_S, const void* d_T);
+
+/* The whole far-zone product y = T G S x (Algorithm 5) for nrhs vectors.
+ * d_x, d_y: [nrhs][sum N_b] complex64 (identity basis: sum N_b =
+ * n_boxes*N_u); y is overwritten. 1 <= nrhs <= the bound max_nrhs.
+ * x and y must not overlap. Errors: UBF_EINVAL (null, aliasing, nrhs out
+ * of range), UBF_ESTATE (unbound), UBF_EDEVICE (launch failed). */
+int ubf_far_mvm(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs,
+                void* hip_stream);
+
+/* Stage 1 alone: d_P[nrhs][n_boxes][N_u] = S_i x_i (complex64). */
+int ubf_aggregate(ubf_plan* plan, const void* d_x, void* d_P, int32_t nrhs,
+                  void* hip_stream);
+
+/* Stage 2 alone: d_E[nrhs][n_boxes][N_u] = sum_{i in F_j} G P_i
+ * (complex64 in and out; d_E overwritten; must not overlap d_P). */
+int ubf_translate(ubf_plan* plan, const void* d_P, void* d_E, int32_t nrhs,
+                  void* hip_stream);
+
+/* Stage 3 alone: d_y[nrhs][sum N_b] = T_j E_j (complex64). */
+int ubf_disaggregate(ubf_plan* plan, const void* d_E, void* d_y,
+                     int32_t nrhs, void* hip_stream);
+
+/* Plan sizes and work counts. Errors: UBF_EINVAL for null pointers. */
+int ubf_plan_info(const ubf_plan* plan, ubf_info* out);
+
+/* Host copy of the distinct offsets w (3*n_offsets int32, in the plan's
+ * offset order). Errors: UBF_EINVAL for null pointers. */
+int ubf_plan_offsets(const ubf_plan* plan, int32_t* out);
+
+/* Host copy of the far set, grouped by offset: for each pair its test box,
+ * source box and offset index (n_pairs int32 each; any may be NULL). */
+int ubf_plan_far_pairs(const ubf_plan* plan, int32_t* test, int32_t* src,
+                       int32_t* offset_index);
+
+/* G_w for offset index `o`, evaluated in FP64 by the plan's generator:
+ * out is N_u*N_u complex values as interleaved doubles, row-major
+ * (row = (l, alpha) test coefficient, column = (s, beta) source).
+ * Errors: UBF_EINVAL (null, o out of range). */
+int ubf_plan_operator(const ubf_plan* plan, int32_t o, double* out);
+
+/* Measurement support (not part of the method). Record HIP timing events
+ * on the call's stream before and after each of the three stages of the
+ * next max_calls ubf_far_mvm calls on this plan (calls beyond that are not
+ * recorded). Errors: UBF_EINVAL (max_calls < 1), UBF_EDEVICE. */
+int ubf_profile_begin(ubf_plan* plan, int32_t max_calls);
+
+/* Wait for the recorded calls and release their events. stage_ms (3
+ * doubles, may be NULL) receives the summed elapsed milliseconds of stage
+ * 1, 2 and 3; call_ms (may be NULL, room for max_calls floats) receives
+ * each call's first-to-last event time; *n_calls (may be NULL) the number
+ * of calls recorded. Errors: UBF_ESTATE (no profile begun), UBF_EDEVICE. */
+int ubf_profile_end(ubf_plan* plan, double* stage_ms, float* call_ms,
+                    int32_t* n_calls);
+
+/* Release the plan (host memory only; the workspace stays the caller's). */
+void ubf_plan_destroy(ubf_plan* plan);
+
+/* Static text for a status code. */
+const char* ubf_status_string(int status);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* ubf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UBF_H */

@@ -60,7 +60,7 @@ def translate(P, boxes, a, k, n_d, mode=FAR_ILIST, eta=ETA0, pairs=None,
     for o, wv in enumerate(uniq):
         sel = np.nonzero(inv == o)[0]
         G = translation_operator(wv, a, k, n_d, eta)
-        contrib = np.einsum("uv,rpv->rpu", G, P[:, i[sel], :])
+        contrib = P[:, i[sel], :] @ G.T              # (nrhs, pairs, N_u)
         np.add.at(E, (slice(None), j[sel]), contrib)
     return E
 

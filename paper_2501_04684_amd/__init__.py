@@ -1,0 +1,299 @@
+"""Far-zone MVM of the uniform-basis group-by-group IE method on MI355X.
+
+Thin ctypes binding of ``libubf.so`` (declared in ``include/ubf.h``). The
+functions carry the C names without the ``ubf_`` prefix and only marshal
+arguments: every stage of the product runs in the library's HIP kernels.
+PyTorch supplies device memory (tensors) and the current stream.
+
+The library must be built (``python -m paper_2501_04684_amd.build``); the
+binding raises ``RuntimeError`` when it is missing instead of falling back
+to any other implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+__all__ = [
+    "UbfError", "FAR_ILIST", "FAR_FULL", "FP32", "lib", "library_path",
+    "declared_symbols", "plan_create", "workspace_bytes", "plan_bind",
+    "plan_set_basis", "far_mvm", "aggregate", "translate", "disaggregate",
+    "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
+    "profile_begin", "profile_end", "plan_destroy", "status_string",
+    "last_error", "FarField",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+HEADER = os.path.join(ROOT, "include", "ubf.h")
+library_path = os.path.join(HERE, "libubf.so")
+
+FAR_ILIST, FAR_FULL = 0, 1
+FP32 = 0
+_MODES = {"ilist": FAR_ILIST, "full": FAR_FULL, FAR_ILIST: FAR_ILIST,
+          FAR_FULL: FAR_FULL}
+
+
+class UbfError(RuntimeError):
+    """A non-zero status from the library, with its thread-local message."""
+
+    def __init__(self, status: int, func: str, message: str):
+        self.status = status
+        super().__init__(f"{func}: {status_string(status)} ({status}): {message}")
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_boxes", ctypes.c_int64), ("box_ijk", ctypes.c_void_p),
+                ("a", ctypes.c_double), ("k", ctypes.c_double),
+                ("eta", ctypes.c_double), ("n_d", ctypes.c_int32),
+                ("far_mode", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_boxes", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("n_offsets", ctypes.c_int32), ("n_orbits", ctypes.c_int32),
+                ("n_u", ctypes.c_int32), ("n_d", ctypes.c_int32),
+                ("n_chunks", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
+                ("translate_flops", ctypes.c_double), ("mfma", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_VP, _I32, _I64, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_SIGS = {
+    "ubf_plan_create": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_VP)]),
+    "ubf_workspace_bytes": (_SZ, [_VP, _I32]),
+    "ubf_plan_bind": (ctypes.c_int, [_VP, _VP, _SZ, _I32, _VP]),
+    "ubf_plan_set_basis": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ubf_far_mvm": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
+    "ubf_aggregate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
+    "ubf_translate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
+    "ubf_disaggregate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
+    "ubf_plan_info": (ctypes.c_int, [_VP, ctypes.POINTER(_Info)]),
+    "ubf_plan_offsets": (ctypes.c_int, [_VP, _VP]),
+    "ubf_plan_far_pairs": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ubf_plan_operator": (ctypes.c_int, [_VP, _I32, _VP]),
+    "ubf_profile_begin": (ctypes.c_int, [_VP, _I32]),
+    "ubf_profile_end": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ubf_plan_destroy": (None, [_VP]),
+    "ubf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ubf_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library (loaded once); RuntimeError if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(
+                f"{library_path} is missing: build it with "
+                "`python -m paper_2501_04684_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(library_path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    """Names of the functions declared in include/ubf.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ubf_[a-z_]+)\s*\(", text)))
+
+
+def status_string(status: int) -> str:
+    return lib().ubf_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().ubf_last_error().decode()
+
+
+def _check(status: int, func: str):
+    if status != 0:
+        raise UbfError(status, func, last_error())
+
+
+def _dev_ptr(t):
+    """Device address of a tensor (or None/0 for NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------------- plans
+
+def plan_create(boxes, a: float, k: float, n_d: int, far_mode="ilist",
+                eta: float = 0.0, precision: int = FP32):
+    """Create a plan from integer box coordinates (n, 3). Host only."""
+    b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 3))
+    prob = _Problem(len(b), b.ctypes.data, float(a), float(k), float(eta),
+                    int(n_d), _MODES[far_mode], int(precision))
+    out = _VP()
+    _check(lib().ubf_plan_create(ctypes.byref(prob), ctypes.byref(out)),
+           "ubf_plan_create")
+    return out.value
+
+
+def workspace_bytes(plan, max_nrhs: int) -> int:
+    return int(lib().ubf_workspace_bytes(plan, int(max_nrhs)))
+
+
+def plan_bind(plan, workspace, max_nrhs: int, stream=None):
+    """Bind a device workspace (a tensor or raw address) of enough bytes."""
+    nbytes = workspace.numel() * workspace.element_size() \
+        if hasattr(workspace, "numel") else workspace_bytes(plan, max_nrhs)
+    _check(lib().ubf_plan_bind(plan, _dev_ptr(workspace), nbytes, int(max_nrhs),
+                               _stream(stream)), "ubf_plan_bind")
+
+
+def plan_set_basis(plan, nb_ptr=None, S=None, T=None):
+    """Set per-box S_i (and optionally T_i); all None = identity basis."""
+    if nb_ptr is None:
+        _check(lib().ubf_plan_set_basis(plan, None, _dev_ptr(S), _dev_ptr(T)),
+               "ubf_plan_set_basis")
+        return
+    nb = np.ascontiguousarray(np.asarray(nb_ptr, dtype=np.int64))
+    _check(lib().ubf_plan_set_basis(plan, nb.ctypes.data, _dev_ptr(S), _dev_ptr(T)),
+           "ubf_plan_set_basis")
+
+
+def _nrhs(x, nrhs):
+    return int(nrhs if nrhs is not None else (x.shape[0] if x.dim() > 1 else 1))
+
+
+def far_mvm(plan, x, y, nrhs=None, stream=None):
+    _check(lib().ubf_far_mvm(plan, _dev_ptr(x), _dev_ptr(y), _nrhs(x, nrhs),
+                             _stream(stream)), "ubf_far_mvm")
+
+
+def aggregate(plan, x, P, nrhs=None, stream=None):
+    _check(lib().ubf_aggregate(plan, _dev_ptr(x), _dev_ptr(P), _nrhs(x, nrhs),
+                               _stream(stream)), "ubf_aggregate")
+
+
+def translate(plan, P, E, nrhs=None, stream=None):
+    _check(lib().ubf_translate(plan, _dev_ptr(P), _dev_ptr(E), _nrhs(P, nrhs),
+                               _stream(stream)), "ubf_translate")
+
+
+def disaggregate(plan, E, y, nrhs=None, stream=None):
+    _check(lib().ubf_disaggregate(plan, _dev_ptr(E), _dev_ptr(y), _nrhs(E, nrhs),
+                                  _stream(stream)), "ubf_disaggregate")
+
+
+def plan_info(plan) -> dict:
+    info = _Info()
+    _check(lib().ubf_plan_info(plan, ctypes.byref(info)), "ubf_plan_info")
+    return {name: getattr(info, name) for name, _ in _Info._fields_
+            if name != "reserved"}
+
+
+def plan_offsets(plan) -> np.ndarray:
+    n = plan_info(plan)["n_offsets"]
+    out = np.zeros((n, 3), dtype=np.int32)
+    _check(lib().ubf_plan_offsets(plan, out.ctypes.data), "ubf_plan_offsets")
+    return out
+
+
+def plan_far_pairs(plan):
+    """(test, src, offset_index) int32 arrays in the plan's grouped order."""
+    n = plan_info(plan)["n_pairs"]
+    t, s, o = (np.zeros(n, dtype=np.int32) for _ in range(3))
+    _check(lib().ubf_plan_far_pairs(plan, t.ctypes.data, s.ctypes.data,
+                                    o.ctypes.data), "ubf_plan_far_pairs")
+    return t, s, o
+
+
+def plan_operator(plan, o: int) -> np.ndarray:
+    nu = plan_info(plan)["n_u"]
+    out = np.zeros((nu, nu), dtype=np.complex128)
+    _check(lib().ubf_plan_operator(plan, int(o), out.ctypes.data),
+           "ubf_plan_operator")
+    return out
+
+
+def profile_begin(plan, max_calls: int):
+    """Start recording per-stage HIP events for the next far_mvm calls."""
+    _check(lib().ubf_profile_begin(plan, int(max_calls)), "ubf_profile_begin")
+
+
+def profile_end(plan, max_calls: int):
+    """(stage_ms[3] summed, per-call ms array) of the recorded calls."""
+    stage = np.zeros(3, dtype=np.float64)
+    calls = np.zeros(max(1, int(max_calls)), dtype=np.float32)
+    n = ctypes.c_int32(0)
+    _check(lib().ubf_profile_end(plan, stage.ctypes.data, calls.ctypes.data,
+                                 ctypes.byref(n)), "ubf_profile_end")
+    return stage, calls[:n.value]
+
+
+def plan_destroy(plan):
+    if plan:
+        lib().ubf_plan_destroy(plan)
+
+
+# ----------------------------------------------------------- convenience
+
+class FarField:
+    """A plan bound to its own device workspace, with an optional basis.
+
+    ``FarField(boxes, a, k, n_d)(x)`` returns ``y = T G S x`` for a complex64
+    CUDA tensor ``x`` of shape [nrhs, sum N_b] (or [sum N_b]).
+    """
+
+    def __init__(self, boxes, a, k, n_d, far_mode="ilist", eta=0.0,
+                 max_nrhs=1, device="cuda"):
+        import torch
+        self.plan = plan_create(boxes, a, k, n_d, far_mode, eta)
+        self.info = plan_info(self.plan)
+        self.max_nrhs = int(max_nrhs)
+        nbytes = workspace_bytes(self.plan, self.max_nrhs)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        addr = self.workspace.data_ptr()
+        self._ws_addr = (addr + 255) & ~255
+        _check(lib().ubf_plan_bind(self.plan, self._ws_addr, nbytes,
+                                   self.max_nrhs, _stream(None)), "ubf_plan_bind")
+        self.nb_total = self.info["n_boxes"] * self.info["n_u"]
+        self._basis = None
+
+    def set_basis(self, nb_ptr=None, S=None, T=None):
+        plan_set_basis(self.plan, nb_ptr, S, T)
+        self._basis = (S, T)  # keep the device matrices alive
+        self.nb_total = (int(np.asarray(nb_ptr)[-1]) if nb_ptr is not None
+                         else self.info["n_boxes"] * self.info["n_u"])
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        x2 = x.reshape(-1, self.nb_total)
+        y = torch.empty_like(x2) if out is None else out
+        far_mvm(self.plan, x2, y, x2.shape[0], stream)
+        return y.reshape(x.shape) if out is None else y
+
+    def close(self):
+        plan_destroy(self.plan)
+        self.plan = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "plan", None):
+                self.close()
+        except Exception:
+            pass

@@ -1,0 +1,366 @@
+// C ABI of the far-zone product (declared in include/ubf.h).
+#include <hip/hip_runtime_api.h>
+
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ubf.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+struct ubf_plan {
+  ubf::Plan p;
+  // Stage timing (ubf_profile_begin/end): 4 events per recorded call.
+  std::vector<hipEvent_t> events;
+  int32_t prof_max = 0;
+  int32_t prof_n = 0;
+  bool profiling = false;
+  ~ubf_plan() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& why) {
+  g_last_error = why;
+  return status;
+}
+
+int ok() {
+  g_last_error.clear();
+  return UBF_OK;
+}
+
+int hip_fail(int err, const char* what) {
+  return fail(UBF_EDEVICE, std::string(what) + ": " +
+                               hipGetErrorString((hipError_t)err));
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+// Common checks of the compute entry points.
+int check_call(ubf_plan* plan, const void* in, void* out, int32_t nrhs,
+               size_t in_bytes, size_t out_bytes) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  if (!in || !out) return fail(UBF_EINVAL, "input or output pointer is NULL");
+  if (!plan->p.ws) return fail(UBF_ESTATE, "plan is not bound to a workspace");
+  if (nrhs < 1 || nrhs > plan->p.max_nrhs)
+    return fail(UBF_EINVAL, "nrhs must be in 1..max_nrhs of the binding (" +
+                                std::to_string(plan->p.max_nrhs) + ")");
+  if (overlaps(in, in_bytes, out, out_bytes))
+    return fail(UBF_EINVAL, "input and output overlap");
+  return UBF_OK;
+}
+
+size_t box_vec_bytes(const ubf::Plan& p, int32_t nrhs) {
+  return (size_t)nrhs * p.n_box * p.nu * 8;
+}
+
+size_t basis_vec_bytes(const ubf::Plan& p, int32_t nrhs) {
+  return (size_t)nrhs * p.nb_total() * 8;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ubf_plan_create(const ubf_problem* problem, ubf_plan** out) {
+  if (!problem || !out) return fail(UBF_EINVAL, "problem or out is NULL");
+  ubf_plan* plan = new (std::nothrow) ubf_plan();
+  if (!plan) return fail(UBF_ENOMEM, "host allocation failed");
+  std::string why;
+  try {
+    why = ubf::build_plan(problem->box_ijk, problem->n_boxes, problem->a,
+                          problem->k, problem->eta, problem->n_d,
+                          problem->far_mode, problem->precision, plan->p);
+  } catch (const std::bad_alloc&) {
+    delete plan;
+    return fail(UBF_ENOMEM, "host allocation failed while building the plan");
+  } catch (...) {
+    delete plan;
+    return fail(UBF_EINVAL, "plan construction failed");
+  }
+  if (!why.empty()) {
+    delete plan;
+    return fail(UBF_EINVAL, why);
+  }
+  *out = plan;
+  return ok();
+}
+
+size_t ubf_workspace_bytes(const ubf_plan* plan, int32_t max_nrhs) {
+  if (!plan || max_nrhs < 1) return 0;
+  return ubf::workspace_layout(plan->p, max_nrhs).total;
+}
+
+int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
+                  int32_t max_nrhs, void* hip_stream) {
+  if (!plan || !d_workspace) return fail(UBF_EINVAL, "plan or workspace is NULL");
+  if (max_nrhs < 1) return fail(UBF_EINVAL, "max_nrhs must be >= 1");
+  if (((uintptr_t)d_workspace & 255) != 0)
+    return fail(UBF_EINVAL, "workspace must be 256-byte aligned");
+  ubf::Plan& p = plan->p;
+  const ubf::Layout L = ubf::workspace_layout(p, max_nrhs);
+  if (bytes < L.total)
+    return fail(UBF_ENOMEM, "workspace too small: need " + std::to_string(L.total) +
+                                " bytes, got " + std::to_string(bytes));
+  char* ws = (char*)d_workspace;
+  hipStream_t s = (hipStream_t)hip_stream;
+  struct Copy {
+    size_t at;
+    const void* src;
+    size_t n;
+  };
+  std::vector<int64_t> nb(p.n_box + 1);
+  if (p.has_basis) {
+    nb = p.nb_ptr;
+  } else {
+    for (int64_t i = 0; i <= p.n_box; ++i) nb[i] = i * p.nu;
+  }
+  const Copy copies[] = {
+      {L.table, p.table.data(), p.table.size() * sizeof(float)},
+      {L.chunks, p.chunks.data(), p.chunks.size() * sizeof(int32_t)},
+      {L.pair_src, p.pair_src.data(), p.pair_src.size() * sizeof(int32_t)},
+      {L.test_ptr, p.test_ptr.data(), p.test_ptr.size() * sizeof(int32_t)},
+      {L.test_pos, p.test_pos.data(), p.test_pos.size() * sizeof(int32_t)},
+      {L.nb_ptr, nb.data(), nb.size() * sizeof(int64_t)},
+  };
+  for (const Copy& c : copies) {
+    if (c.n == 0) continue;
+    hipError_t e = hipMemcpyAsync(ws + c.at, c.src, c.n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (bind)");
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (bind)");
+  p.ws = ws;
+  p.ws_bytes = bytes;
+  p.max_nrhs = max_nrhs;
+  p.d_table = (float*)(ws + L.table);
+  p.d_chunks = (int32_t*)(ws + L.chunks);
+  p.d_pair_src = (int32_t*)(ws + L.pair_src);
+  p.d_test_ptr = (int32_t*)(ws + L.test_ptr);
+  p.d_test_pos = (int32_t*)(ws + L.test_pos);
+  p.d_nb_ptr = (int64_t*)(ws + L.nb_ptr);
+  p.d_P = (float*)(ws + L.P);
+  p.d_part = (float*)(ws + L.part);
+  return ok();
+}
+
+int ubf_plan_set_basis(ubf_plan* plan, const int64_t* nb_ptr, const void* d_S,
+                       const void* d_T) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  ubf::Plan& p = plan->p;
+  if (!nb_ptr && !d_S && !d_T) {
+    if (!p.ws) return fail(UBF_ESTATE, "plan is not bound to a workspace");
+    std::vector<int64_t> nb(p.n_box + 1);
+    for (int64_t i = 0; i <= p.n_box; ++i) nb[i] = i * p.nu;
+    hipError_t e = hipMemcpy(p.d_nb_ptr, nb.data(), nb.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (set_basis)");
+    p.has_basis = false;
+    p.nb_ptr.clear();
+    p.d_S = p.d_T = nullptr;
+    return ok();
+  }
+  if (!nb_ptr || !d_S) return fail(UBF_EINVAL, "nb_ptr and d_S are both required");
+  if (nb_ptr[0] != 0) return fail(UBF_EINVAL, "nb_ptr[0] must be 0");
+  for (int64_t i = 0; i < p.n_box; ++i)
+    if (nb_ptr[i + 1] < nb_ptr[i]) return fail(UBF_EINVAL, "nb_ptr must be non-decreasing");
+  if (nb_ptr[p.n_box] > (int64_t(1) << 40)) return fail(UBF_EINVAL, "too many basis functions");
+  if (!p.ws) return fail(UBF_ESTATE, "plan is not bound to a workspace");
+  hipError_t e = hipMemcpy(p.d_nb_ptr, nb_ptr, (p.n_box + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy (set_basis)");
+  p.nb_ptr.assign(nb_ptr, nb_ptr + p.n_box + 1);
+  p.has_basis = true;
+  p.d_S = d_S;
+  p.d_T = d_T;
+  return ok();
+}
+
+int ubf_far_mvm(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs,
+                void* hip_stream) {
+  int st = check_call(plan, d_x, d_y, nrhs,
+                      plan ? basis_vec_bytes(plan->p, nrhs) : 0,
+                      plan ? basis_vec_bytes(plan->p, nrhs) : 0);
+  if (st != UBF_OK) return st;
+  const ubf::Plan& p = plan->p;
+  hipEvent_t* ev = nullptr;
+  if (plan->profiling && plan->prof_n < plan->prof_max)
+    ev = &plan->events[4 * (size_t)plan->prof_n++];
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  int e = ubf::launch_aggregate(p, d_x, p.d_P, nrhs, hip_stream);
+  if (e) return hip_fail(e, "aggregate launch");
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  e = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, hip_stream);
+  if (e) return hip_fail(e, "translate launch");
+  if (ev && hipEventRecord(ev[2], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  e = ubf::launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, hip_stream);
+  if (e) return hip_fail(e, "disaggregate launch");
+  if (ev && hipEventRecord(ev[3], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  return ok();
+}
+
+int ubf_profile_begin(ubf_plan* plan, int32_t max_calls) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  if (max_calls < 1) return fail(UBF_EINVAL, "max_calls must be >= 1");
+  for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
+  plan->events.clear();
+  plan->profiling = false;
+  plan->events.reserve(4 * (size_t)max_calls);
+  for (size_t i = 0; i < 4 * (size_t)max_calls; ++i) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+    plan->events.push_back(e);
+  }
+  plan->prof_max = max_calls;
+  plan->prof_n = 0;
+  plan->profiling = true;
+  return ok();
+}
+
+int ubf_profile_end(ubf_plan* plan, double* stage_ms, float* call_ms,
+                    int32_t* n_calls) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  if (!plan->profiling) return fail(UBF_ESTATE, "no profile begun");
+  plan->profiling = false;
+  double sum[3] = {0, 0, 0};
+  for (int32_t c = 0; c < plan->prof_n; ++c) {
+    hipEvent_t* ev = &plan->events[4 * (size_t)c];
+    hipError_t err = hipEventSynchronize(ev[3]);
+    if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize");
+    for (int st = 0; st < 3; ++st) {
+      float ms = 0.f;
+      err = hipEventElapsedTime(&ms, ev[st], ev[st + 1]);
+      if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
+      sum[st] += ms;
+    }
+    if (call_ms) {
+      err = hipEventElapsedTime(&call_ms[c], ev[0], ev[3]);
+      if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
+    }
+  }
+  if (stage_ms)
+    for (int st = 0; st < 3; ++st) stage_ms[st] = sum[st];
+  if (n_calls) *n_calls = plan->prof_n;
+  for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
+  plan->events.clear();
+  return ok();
+}
+
+int ubf_aggregate(ubf_plan* plan, const void* d_x, void* d_P, int32_t nrhs,
+                  void* hip_stream) {
+  int st = check_call(plan, d_x, d_P, nrhs,
+                      plan ? basis_vec_bytes(plan->p, nrhs) : 0,
+                      plan ? box_vec_bytes(plan->p, nrhs) : 0);
+  if (st != UBF_OK) return st;
+  const ubf::Plan& p = plan->p;
+  int e = ubf::launch_aggregate(p, d_x, p.d_P, nrhs, hip_stream);
+  if (e) return hip_fail(e, "aggregate launch");
+  e = ubf::launch_unpack(p, p.d_P, d_P, nrhs, hip_stream);
+  if (e) return hip_fail(e, "unpack launch");
+  return ok();
+}
+
+int ubf_translate(ubf_plan* plan, const void* d_P, void* d_E, int32_t nrhs,
+                  void* hip_stream) {
+  int st = check_call(plan, d_P, d_E, nrhs,
+                      plan ? box_vec_bytes(plan->p, nrhs) : 0,
+                      plan ? box_vec_bytes(plan->p, nrhs) : 0);
+  if (st != UBF_OK) return st;
+  const ubf::Plan& p = plan->p;
+  // Stage 2 alone maps box vectors to box vectors whatever the basis.
+  int e = ubf::launch_pack(p, d_P, p.d_P, nrhs, hip_stream);
+  if (e) return hip_fail(e, "pack launch");
+  e = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, hip_stream);
+  if (e) return hip_fail(e, "translate launch");
+  e = ubf::launch_disaggregate(p, true, p.d_part, nullptr, d_E, nrhs, hip_stream,
+                               /*identity=*/true);
+  if (e) return hip_fail(e, "reduce launch");
+  return ok();
+}
+
+int ubf_disaggregate(ubf_plan* plan, const void* d_E, void* d_y, int32_t nrhs,
+                     void* hip_stream) {
+  int st = check_call(plan, d_E, d_y, nrhs,
+                      plan ? box_vec_bytes(plan->p, nrhs) : 0,
+                      plan ? basis_vec_bytes(plan->p, nrhs) : 0);
+  if (st != UBF_OK) return st;
+  const ubf::Plan& p = plan->p;
+  int e = ubf::launch_disaggregate(p, false, nullptr, d_E, d_y, nrhs, hip_stream);
+  if (e) return hip_fail(e, "disaggregate launch");
+  return ok();
+}
+
+int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
+  if (!plan || !out) return fail(UBF_EINVAL, "plan or out is NULL");
+  const ubf::Plan& p = plan->p;
+  std::memset(out, 0, sizeof(*out));
+  out->n_boxes = p.n_box;
+  out->n_pairs = p.n_pairs();
+  out->n_offsets = p.n_off();
+  out->n_orbits = p.n_orbits;
+  out->n_u = p.nu;
+  out->n_d = p.n_d;
+  out->n_chunks = p.n_chunks();
+  out->table_bytes = (int64_t)(p.table.size() * sizeof(float));
+  out->translate_flops = 8.0 * p.nu * (double)p.nu * (double)p.n_pairs();
+  out->mfma = ubf::translate_uses_mfma(p) ? 1 : 0;
+  return ok();
+}
+
+int ubf_plan_offsets(const ubf_plan* plan, int32_t* out) {
+  if (!plan || !out) return fail(UBF_EINVAL, "plan or out is NULL");
+  std::memcpy(out, plan->p.offsets.data(), plan->p.offsets.size() * sizeof(int32_t));
+  return ok();
+}
+
+int ubf_plan_far_pairs(const ubf_plan* plan, int32_t* test, int32_t* src,
+                       int32_t* offset_index) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  const ubf::Plan& p = plan->p;
+  const size_t n = p.pair_src.size() * sizeof(int32_t);
+  if (test) std::memcpy(test, p.pair_test.data(), n);
+  if (src) std::memcpy(src, p.pair_src.data(), n);
+  if (offset_index) std::memcpy(offset_index, p.pair_off.data(), n);
+  return ok();
+}
+
+int ubf_plan_operator(const ubf_plan* plan, int32_t o, double* out) {
+  if (!plan || !out) return fail(UBF_EINVAL, "plan or out is NULL");
+  const ubf::Plan& p = plan->p;
+  if (o < 0 || o >= p.n_off()) return fail(UBF_EINVAL, "offset index out of range");
+  std::vector<std::complex<double>> G;
+  ubf::operator_fp64(&p.offsets[3 * o], p.a, p.k, p.eta, p.n_d, G);
+  std::memcpy(out, G.data(), G.size() * sizeof(std::complex<double>));
+  return ok();
+}
+
+void ubf_plan_destroy(ubf_plan* plan) { delete plan; }
+
+const char* ubf_status_string(int status) {
+  switch (status) {
+    case UBF_OK: return "ok";
+    case UBF_EINVAL: return "invalid argument";
+    case UBF_ENOMEM: return "out of memory (workspace too small or host allocation failed)";
+    case UBF_EDEVICE: return "HIP runtime error";
+    case UBF_ESTATE: return "plan not bound / invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* ubf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

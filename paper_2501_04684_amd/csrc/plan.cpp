@@ -1,0 +1,288 @@
+// Host plan builder: validation, far set (Algorithm 2), offset grouping,
+// symmetry orbits (Sec. 2.2) and the FP32 operator table (Eq. 5-6, 13).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <unordered_map>
+
+namespace ubf {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kEta0 = 376.730313668;
+// Dense box-index grids above this many cells use a hash map instead.
+constexpr int64_t kDenseCells = int64_t(1) << 24;
+// Largest operator table accepted (bytes).
+constexpr double kMaxTableBytes = 16.0 * (1ull << 30);
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Lookup of a box index from integer coordinates.
+struct BoxIndex {
+  int32_t nx = 0, ny = 0, nz = 0;
+  std::vector<int32_t> dense;
+  std::unordered_map<uint64_t, int32_t> sparse;
+  bool use_dense = true;
+
+  static uint64_t key(int64_t x, int64_t y, int64_t z) {
+    return (uint64_t(x) << 42) ^ (uint64_t(y) << 21) ^ uint64_t(z);
+  }
+  // Returns false on a duplicate coordinate.
+  bool build(const std::vector<int32_t>& b, int64_t n) {
+    int32_t mx = 0, my = 0, mz = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      mx = std::max(mx, b[3 * i]);
+      my = std::max(my, b[3 * i + 1]);
+      mz = std::max(mz, b[3 * i + 2]);
+    }
+    nx = mx + 1;
+    ny = my + 1;
+    nz = mz + 1;
+    use_dense = (int64_t)nx * ny * nz <= kDenseCells;
+    if (use_dense) {
+      dense.assign((size_t)nx * ny * nz, -1);
+      for (int64_t i = 0; i < n; ++i) {
+        int32_t& slot = dense[((size_t)b[3 * i] * ny + b[3 * i + 1]) * nz + b[3 * i + 2]];
+        if (slot >= 0) return false;
+        slot = (int32_t)i;
+      }
+    } else {
+      sparse.reserve((size_t)n * 2);
+      for (int64_t i = 0; i < n; ++i)
+        if (!sparse.emplace(key(b[3 * i], b[3 * i + 1], b[3 * i + 2]), (int32_t)i).second)
+          return false;
+    }
+    return true;
+  }
+  int32_t find(int64_t x, int64_t y, int64_t z) const {
+    if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) return -1;
+    if (use_dense) return dense[((size_t)x * ny + y) * nz + z];
+    auto it = sparse.find(key(x, y, z));
+    return it == sparse.end() ? -1 : it->second;
+  }
+};
+
+int32_t cheb(int64_t x, int64_t y, int64_t z) {
+  return (int32_t)std::max({std::llabs(x), std::llabs(y), std::llabs(z)});
+}
+
+int64_t floordiv2(int64_t c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
+
+}  // namespace
+
+void dyadic_green(const double R[3], double k, double eta,
+                  std::complex<double> D[3][3]) {
+  const double r = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+  const double rh[3] = {R[0] / r, R[1] / r, R[2] / r};
+  const double kr = k * r;
+  const std::complex<double> j(0.0, 1.0);
+  const std::complex<double> psi =
+      -j * k * eta * std::exp(-j * kr) / (4.0 * kPi * r);
+  const std::complex<double> c_iso = 1.0 - j / kr - 1.0 / (kr * kr);
+  const std::complex<double> c_rr = 1.0 - 3.0 * j / kr - 3.0 / (kr * kr);
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 3; ++q)
+      D[p][q] = psi * ((p == q ? c_iso : 0.0) - rh[p] * rh[q] * c_rr);
+}
+
+std::vector<double> site_offsets(double a, int n_d) {
+  std::vector<double> r;
+  r.reserve(3 * n_d * n_d * n_d);
+  for (int mx = 0; mx < n_d; ++mx)
+    for (int my = 0; my < n_d; ++my)
+      for (int mz = 0; mz < n_d; ++mz) {
+        r.push_back(a * ((mx + 0.5) / n_d - 0.5));
+        r.push_back(a * ((my + 0.5) / n_d - 0.5));
+        r.push_back(a * ((mz + 0.5) / n_d - 0.5));
+      }
+  return r;
+}
+
+void operator_fp64(const int32_t w[3], double a, double k, double eta, int n_d,
+                   std::vector<std::complex<double>>& G) {
+  const std::vector<double> r = site_offsets(a, n_d);
+  const int nd3 = n_d * n_d * n_d, nu = 3 * nd3;
+  G.assign((size_t)nu * nu, 0.0);
+  std::complex<double> D[3][3];
+  for (int l = 0; l < nd3; ++l)
+    for (int s = 0; s < nd3; ++s) {
+      const double R[3] = {a * w[0] + r[3 * l] - r[3 * s],
+                           a * w[1] + r[3 * l + 1] - r[3 * s + 1],
+                           a * w[2] + r[3 * l + 2] - r[3 * s + 2]};
+      dyadic_green(R, k, eta, D);
+      for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be)
+          G[(size_t)(3 * l + al) * nu + 3 * s + be] = D[al][be];
+    }
+}
+
+Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
+  Layout L{};
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t here = at;
+    at = align256(at + bytes);
+    return here;
+  };
+  L.table = take(p.table.size() * sizeof(float));
+  L.chunks = take(p.chunks.size() * sizeof(int32_t));
+  L.pair_src = take(p.pair_src.size() * sizeof(int32_t));
+  L.test_ptr = take(p.test_ptr.size() * sizeof(int32_t));
+  L.test_pos = take(p.test_pos.size() * sizeof(int32_t));
+  L.nb_ptr = take((size_t)(p.n_box + 1) * sizeof(int64_t));
+  L.P = take((size_t)max_nrhs * p.n_box * p.pstride() * sizeof(float));
+  L.part = take((size_t)max_nrhs * p.n_pairs() * p.pstride() * sizeof(float));
+  L.total = at;
+  return L;
+}
+
+std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
+                       double k, double eta, int n_d, int far_mode,
+                       int precision, Plan& P) {
+  if (!box_ijk) return "box_ijk is NULL";
+  if (n_box < 1) return "n_boxes must be >= 1";
+  if (n_box > std::numeric_limits<int32_t>::max() / 2) return "n_boxes too large";
+  if (!(a > 0.0) || !std::isfinite(a)) return "box side a must be > 0";
+  if (!(k > 0.0) || !std::isfinite(k)) return "wavenumber k must be > 0";
+  if (!(eta >= 0.0) || !std::isfinite(eta)) return "eta must be >= 0 (0 = free space)";
+  if (n_d < 1 || n_d > 4) return "n_d must be in 1..4";
+  if (far_mode != 0 && far_mode != 1) return "unknown far_mode";
+  if (precision != 0) return "unknown precision";
+
+  P.n_box = n_box;
+  P.boxes.assign(box_ijk, box_ijk + 3 * n_box);
+  for (int64_t i = 0; i < 3 * n_box; ++i)
+    if (P.boxes[i] < 0) return "box coordinates must be >= 0";
+  P.a = a;
+  P.k = k;
+  P.eta = eta == 0.0 ? kEta0 : eta;
+  P.n_d = n_d;
+  P.nu = 3 * n_d * n_d * n_d;
+  P.kh = half_len(P.nu);
+  P.far_mode = far_mode;
+  P.precision = precision;
+
+  BoxIndex index;
+  if (!index.build(P.boxes, n_box)) return "duplicate box coordinates";
+  const int32_t* b = P.boxes.data();
+
+  // Far set: (test j, source i, offset w = c_j - c_i), test-major.
+  std::vector<int32_t> pj, pi;
+  std::vector<std::array<int32_t, 3>> pw;
+  const int64_t kMaxPairs = std::numeric_limits<int32_t>::max();
+  if (far_mode == 0) {
+    for (int64_t j = 0; j < n_box; ++j) {
+      const int64_t cx = b[3 * j], cy = b[3 * j + 1], cz = b[3 * j + 2];
+      for (int wx = -3; wx <= 3; ++wx)
+        for (int wy = -3; wy <= 3; ++wy)
+          for (int wz = -3; wz <= 3; ++wz) {
+            if (cheb(wx, wy, wz) < 2) continue;
+            const int64_t sx = cx - wx, sy = cy - wy, sz = cz - wz;
+            const int32_t i = index.find(sx, sy, sz);
+            if (i < 0) continue;
+            if (cheb(floordiv2(cx) - floordiv2(sx), floordiv2(cy) - floordiv2(sy),
+                     floordiv2(cz) - floordiv2(sz)) > 1)
+              continue;
+            pj.push_back((int32_t)j);
+            pi.push_back(i);
+            pw.push_back({wx, wy, wz});
+          }
+    }
+  } else {
+    for (int64_t j = 0; j < n_box; ++j)
+      for (int64_t i = 0; i < n_box; ++i) {
+        const int64_t wx = (int64_t)b[3 * j] - b[3 * i];
+        const int64_t wy = (int64_t)b[3 * j + 1] - b[3 * i + 1];
+        const int64_t wz = (int64_t)b[3 * j + 2] - b[3 * i + 2];
+        if (cheb(wx, wy, wz) < 2) continue;
+        if ((int64_t)pj.size() >= kMaxPairs) return "far set exceeds 2^31-1 pairs";
+        pj.push_back((int32_t)j);
+        pi.push_back((int32_t)i);
+        pw.push_back({(int32_t)wx, (int32_t)wy, (int32_t)wz});
+      }
+  }
+  if ((int64_t)pj.size() > kMaxPairs) return "far set exceeds 2^31-1 pairs";
+
+  // Distinct offsets, lexicographic.
+  std::vector<std::array<int32_t, 3>> uniq(pw);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  const int64_t n_off = (int64_t)uniq.size();
+  const double table_bytes = (double)n_off * 2.0 * (P.nu + 1) * P.kh * sizeof(float);
+  if (table_bytes > kMaxTableBytes) return "operator table would exceed 16 GiB";
+  P.offsets.resize(3 * n_off);
+  for (int64_t o = 0; o < n_off; ++o)
+    for (int d = 0; d < 3; ++d) P.offsets[3 * o + d] = uniq[o][d];
+
+  // Offset index of every pair, then a stable counting sort by offset.
+  const int64_t np = (int64_t)pj.size();
+  std::vector<int32_t> oid(np);
+  for (int64_t p = 0; p < np; ++p)
+    oid[p] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), pw[p]) - uniq.begin());
+  P.off_ptr.assign(n_off + 1, 0);
+  for (int64_t p = 0; p < np; ++p) P.off_ptr[oid[p] + 1]++;
+  for (int64_t o = 0; o < n_off; ++o) P.off_ptr[o + 1] += P.off_ptr[o];
+  std::vector<int64_t> fill(P.off_ptr.begin(), P.off_ptr.end() - 1);
+  P.pair_test.resize(np);
+  P.pair_src.resize(np);
+  P.pair_off.resize(np);
+  for (int64_t p = 0; p < np; ++p) {
+    const int64_t at = fill[oid[p]]++;
+    P.pair_test[at] = pj[p];
+    P.pair_src[at] = pi[p];
+    P.pair_off[at] = oid[p];
+  }
+
+  // Test box -> positions of its pairs in the grouped order.
+  P.test_ptr.assign(n_box + 1, 0);
+  for (int64_t p = 0; p < np; ++p) P.test_ptr[P.pair_test[p] + 1]++;
+  for (int64_t j = 0; j < n_box; ++j) P.test_ptr[j + 1] += P.test_ptr[j];
+  std::vector<int32_t> tfill(P.test_ptr.begin(), P.test_ptr.end() - 1);
+  P.test_pos.resize(np);
+  for (int64_t p = 0; p < np; ++p) P.test_pos[tfill[P.pair_test[p]]++] = (int32_t)p;
+
+  // Work units: up to kChunk consecutive pairs of one offset.
+  P.chunks.clear();
+  for (int64_t o = 0; o < n_off; ++o)
+    for (int64_t s = P.off_ptr[o]; s < P.off_ptr[o + 1]; s += kChunk) {
+      P.chunks.push_back((int32_t)o);
+      P.chunks.push_back((int32_t)s);
+      P.chunks.push_back((int32_t)std::min<int64_t>(kChunk, P.off_ptr[o + 1] - s));
+      P.chunks.push_back(0);
+    }
+
+  // Orbits under the 48 signed permutations: key = sorted |w|.
+  std::vector<std::array<int32_t, 3>> keys(n_off);
+  for (int64_t o = 0; o < n_off; ++o) {
+    std::array<int32_t, 3> kk = {std::abs(uniq[o][0]), std::abs(uniq[o][1]),
+                                 std::abs(uniq[o][2])};
+    std::sort(kk.begin(), kk.end());
+    keys[o] = kk;
+  }
+  std::sort(keys.begin(), keys.end());
+  P.n_orbits = (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
+
+  // Operator table image.
+  const size_t plane = P.plane_floats();
+  P.table.assign((size_t)n_off * 2 * plane, 0.0f);
+  std::vector<std::complex<double>> G;
+  for (int64_t o = 0; o < n_off; ++o) {
+    operator_fp64(&P.offsets[3 * o], P.a, P.k, P.eta, n_d, G);
+    float* re = &P.table[(size_t)o * 2 * plane];
+    float* im = re + plane;
+    for (int u = 0; u < P.nu; ++u)
+      for (int v = 0; v < P.nu; ++v) {
+        re[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].real();
+        im[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].imag();
+      }
+  }
+  return std::string();
+}
+
+}  // namespace ubf

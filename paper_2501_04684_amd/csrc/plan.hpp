@@ -1,0 +1,99 @@
+// Host-side plan of the far-zone product: geometry, far set, work
+// partition and the operator table image. Everything here runs on the CPU
+// at plan creation; nothing touches a device.
+#pragma once
+
+#include <complex>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ubf {
+
+// Columns (box pairs) per translation work unit: four wavefronts of 16.
+constexpr int kChunk = 64;
+
+// Padded half-length of a planar box vector: N_u + 1 rounded up to even.
+// A box vector is stored as [re(N_u), 0 pad | im(N_u), 0 pad], 2*kh floats.
+inline int half_len(int nu) { return (nu + 2) & ~1; }
+
+// Free-space dyadic Green's function of Eq. (5)-(6), FP64, time
+// convention exp(+j omega t): D(R) = psi(R) { I (1 - j/kR - 1/(kR)^2)
+//   - Rhat Rhat (1 - 3j/kR - 3/(kR)^2) },  psi = -j k eta e^{-jkR}/(4 pi R).
+void dyadic_green(const double R[3], double k, double eta,
+                  std::complex<double> D[3][3]);
+
+// Cell-centred site offsets from the box centre, site s = (mx*n_d+my)*n_d+mz.
+std::vector<double> site_offsets(double a, int n_d);
+
+// G_w in FP64, row-major n_u x n_u complex: entry ((l,alpha),(s,beta)) is
+// D(a*w + r_l - r_s)[alpha][beta] (Eq. 12-13).
+void operator_fp64(const int32_t w[3], double a, double k, double eta, int n_d,
+                   std::vector<std::complex<double>>& G);
+
+struct Plan {
+  // Problem.
+  int64_t n_box = 0;
+  std::vector<int32_t> boxes;  // 3 * n_box
+  double a = 0, k = 0, eta = 0;
+  int n_d = 0, nu = 0, kh = 0, far_mode = 0, precision = 0;
+
+  // Far set, grouped by offset (offset index ascending, then test box).
+  std::vector<int32_t> offsets;    // 3 * n_off, lexicographic order
+  std::vector<int64_t> off_ptr;    // n_off + 1
+  std::vector<int32_t> pair_test;  // n_pairs
+  std::vector<int32_t> pair_src;   // n_pairs
+  std::vector<int32_t> pair_off;   // n_pairs
+  std::vector<int32_t> test_ptr;   // n_box + 1: pairs of each test box ...
+  std::vector<int32_t> test_pos;   // ... as positions in the grouped order
+  std::vector<int32_t> chunks;     // 4 per chunk: offset, begin, count, 0
+  int32_t n_orbits = 0;
+
+  // Operator table image: per offset two planes (re, im) of (nu+1) rows of
+  // kh floats; row nu and columns >= nu are zero.
+  std::vector<float> table;
+
+  int64_t n_pairs() const { return (int64_t)pair_src.size(); }
+  int32_t n_off() const { return (int32_t)(offsets.size() / 3); }
+  int64_t n_chunks() const { return (int64_t)(chunks.size() / 4); }
+  size_t plane_floats() const { return (size_t)(nu + 1) * kh; }
+  size_t op_floats() const { return 2 * plane_floats(); }
+  int pstride() const { return 2 * kh; }
+
+  // Binding.
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t max_nrhs = 0;
+  // Device pointers into the workspace.
+  float* d_table = nullptr;
+  int32_t* d_chunks = nullptr;
+  int32_t* d_pair_src = nullptr;
+  int32_t* d_test_ptr = nullptr;
+  int32_t* d_test_pos = nullptr;
+  int64_t* d_nb_ptr = nullptr;
+  float* d_P = nullptr;
+  float* d_part = nullptr;
+
+  // Basis.
+  bool has_basis = false;
+  std::vector<int64_t> nb_ptr;  // n_box + 1
+  const void* d_S = nullptr;
+  const void* d_T = nullptr;
+  int64_t nb_total() const {
+    return has_basis ? nb_ptr.back() : n_box * (int64_t)nu;
+  }
+};
+
+// Workspace layout, in bytes from the workspace start.
+struct Layout {
+  size_t table, chunks, pair_src, test_ptr, test_pos, nb_ptr, P, part, total;
+};
+Layout workspace_layout(const Plan& p, int32_t max_nrhs);
+
+// Validate and build; returns an empty string on success, else the reason.
+std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
+                       double k, double eta, int n_d, int far_mode,
+                       int precision, Plan& out);
+
+}  // namespace ubf

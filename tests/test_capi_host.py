@@ -1,0 +1,179 @@
+"""Host-side checks of the C-ABI library: symbols, validation, plan tables.
+
+Nothing here launches a kernel; plan creation and its accessors run on the
+CPU only.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2501_04684_amd as U
+import workloads as W
+
+A, K = 0.25, 2 * np.pi
+
+
+def test_library_exports_every_declared_symbol():
+    L = U.lib()
+    names = U.declared_symbols()
+    assert len(names) == 17
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    assert U.status_string(0) == "ok"
+    for st in (-1, -2, -3, -4):
+        assert U.status_string(st) not in ("ok", "unknown status")
+    assert U.status_string(-99) == "unknown status"
+
+
+@pytest.mark.parametrize("kwargs,msg", [
+    (dict(boxes=np.zeros((0, 3))), "n_boxes"),
+    (dict(boxes=np.array([[0, 0, 0], [0, 0, 0]])), "duplicate"),
+    (dict(boxes=np.array([[0, -1, 0]])), ">= 0"),
+    (dict(a=0.0), "box side"),
+    (dict(a=-1.0), "box side"),
+    (dict(k=0.0), "wavenumber"),
+    (dict(k=float("nan")), "wavenumber"),
+    (dict(n_d=0), "n_d"),
+    (dict(n_d=5), "n_d"),
+    (dict(far_mode=7), "far_mode"),
+    (dict(eta=-1.0), "eta"),
+])
+def test_plan_create_rejects(kwargs, msg):
+    args = dict(boxes=W.grid_boxes(2, 2, 2), a=A, k=K, n_d=3, far_mode="ilist")
+    args.update(kwargs)
+    fm = args.pop("far_mode")
+    boxes = args.pop("boxes")
+    if isinstance(fm, int) and fm not in (0, 1):
+        b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32))
+        prob = U._Problem(len(b), b.ctypes.data, args["a"], args["k"], 0.0,
+                          args["n_d"], fm, 0)
+        out = ctypes.c_void_p()
+        st = U.lib().ubf_plan_create(ctypes.byref(prob), ctypes.byref(out))
+        assert st == -1 and msg in U.last_error() and not out.value
+        return
+    with pytest.raises(U.UbfError) as e:
+        U.plan_create(boxes, far_mode=fm, **args)
+    assert e.value.status == -1
+    assert msg in str(e.value)
+
+
+def test_null_arguments_rejected_before_any_device_call():
+    L = U.lib()
+    out = ctypes.c_void_p()
+    assert L.ubf_plan_create(None, ctypes.byref(out)) == -1
+    assert L.ubf_workspace_bytes(None, 1) == 0
+    assert L.ubf_plan_bind(None, None, 0, 1, None) == -1
+    assert L.ubf_far_mvm(None, None, None, 1, None) == -1
+    assert L.ubf_plan_info(None, None) == -1
+    assert L.ubf_profile_begin(None, 1) == -1
+    assert L.ubf_profile_end(None, None, None, None) == -1
+    plan = U.plan_create(W.grid_boxes(2, 2, 2), A, K, 2)
+    try:
+        # unbound plan: state error, not a device call
+        assert L.ubf_far_mvm(plan, 1 << 20, 2 << 20, 1, None) == -4
+        assert L.ubf_translate(plan, 1 << 20, 2 << 20, 1, None) == -4
+        assert L.ubf_plan_set_basis(plan, None, None, None) == -4
+        # bad workspace: misaligned, too small
+        assert L.ubf_plan_bind(plan, 1 << 20 | 8, 1 << 30, 1, None) == -1
+        assert L.ubf_plan_bind(plan, 1 << 20, 16, 1, None) == -2
+        assert "too small" in U.last_error()
+        assert L.ubf_plan_bind(plan, 1 << 20, 1 << 30, 0, None) == -1
+        assert L.ubf_workspace_bytes(plan, 0) == 0
+        assert L.ubf_plan_operator(plan, 10 ** 6, None) == -1
+        assert L.ubf_profile_begin(plan, 0) == -1
+        assert L.ubf_profile_end(plan, None, None, None) == -4
+    finally:
+        U.plan_destroy(plan)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_plan_far_set_matches_oracle(cfg):
+    w = W.config(cfg)
+    plan = U.plan_create(w.boxes, w.a, w.k, w.n_d, w.far_mode)
+    try:
+        info = U.plan_info(plan)
+        j, i, off = O.far_pairs(w.boxes, w.far_mode)
+        uniq, _ = O.offset_ids(off)
+        assert info["n_pairs"] == len(j)
+        assert info["n_offsets"] == len(uniq)
+        assert info["n_orbits"] == len(O.symmetry.orbits(uniq))
+        assert info["n_u"] == 81 and info["mfma"] == 1
+        assert info["translate_flops"] == 8 * 81 * 81 * len(j)
+        t, s, o = U.plan_far_pairs(plan)
+        offs = U.plan_offsets(plan)
+        got = sorted(zip(t.tolist(), s.tolist(), map(tuple, offs[o].tolist())))
+        ref = sorted(zip(j.tolist(), i.tolist(), map(tuple, off.tolist())))
+        assert got == ref
+        # grouped by offset, each offset's pairs in test-box order
+        assert np.all(np.diff(o) >= 0)
+        for oo in np.unique(o)[:20]:
+            assert np.all(np.diff(t[o == oo]) > 0)
+        # the work partition covers every pair once
+        assert info["n_chunks"] >= -(-len(j) // 64)
+    finally:
+        U.plan_destroy(plan)
+
+
+def test_full_mode_and_orbits():
+    b = W.grid_boxes(6, 6, 6)
+    plan = U.plan_create(b, A, K, 1, "full")
+    try:
+        info = U.plan_info(plan)
+        assert (info["n_pairs"], info["n_offsets"], info["n_orbits"]) == (42560, 1304, 52)
+    finally:
+        U.plan_destroy(plan)
+
+
+@pytest.mark.parametrize("n_d", [1, 2, 3, 4])
+def test_host_operators_match_oracle(n_d):
+    b = W.grid_boxes(4, 4, 4)
+    plan = U.plan_create(b, A, K, n_d, "ilist")
+    try:
+        offs = U.plan_offsets(plan)
+        for o in (0, 7, 100, 315):
+            G = U.plan_operator(plan, o)
+            ref = O.translation_operator(offs[o], A, K, n_d)
+            assert np.abs(G - ref).max() <= 1e-13 * np.abs(ref).max()
+    finally:
+        U.plan_destroy(plan)
+
+
+def test_low_frequency_operator():
+    # a = lambda/256 regime of the low-frequency example (Sec. 5)
+    b = W.grid_boxes(4, 4, 4)
+    a = 1.0 / 256
+    plan = U.plan_create(b, a, K, 3, "ilist", eta=1.0)
+    try:
+        offs = U.plan_offsets(plan)
+        for o in (0, 200):
+            G = U.plan_operator(plan, o)
+            ref = O.translation_operator(offs[o], a, K, 3, eta=1.0)
+            assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        U.plan_destroy(plan)
+
+
+def test_workspace_grows_with_nrhs():
+    plan = U.plan_create(W.grid_boxes(4, 4, 4), A, K, 3)
+    try:
+        w1, w2 = U.workspace_bytes(plan, 1), U.workspace_bytes(plan, 2)
+        assert 0 < w1 < w2 and w1 % 256 == 0
+    finally:
+        U.plan_destroy(plan)
+
+
+def test_sparse_coordinates_use_hash_index():
+    # coordinates far apart: dense index grid would be enormous
+    b = np.array([[0, 0, 0], [0, 0, 2], [4000, 4000, 4000], [4000, 4000, 4003]])
+    plan = U.plan_create(b, A, K, 1, "full")
+    try:
+        t, s, _ = U.plan_far_pairs(plan)
+        j, i, _ = O.far_pairs(b, "full")
+        assert sorted(zip(t, s)) == sorted(zip(j, i))
+    finally:
+        U.plan_destroy(plan)
