@@ -130,9 +130,10 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
   const Copy copies[] = {
       {L.table, p.table.data(), p.table.size() * sizeof(float)},
       {L.chunks, p.chunks.data(), p.chunks.size() * sizeof(int32_t)},
+      {L.wg_ptr, p.wg_ptr.data(), p.wg_ptr.size() * sizeof(int32_t)},
       {L.pair_src, p.pair_src.data(), p.pair_src.size() * sizeof(int32_t)},
+      {L.pair_dst, p.pair_dst.data(), p.pair_dst.size() * sizeof(int32_t)},
       {L.test_ptr, p.test_ptr.data(), p.test_ptr.size() * sizeof(int32_t)},
-      {L.test_pos, p.test_pos.data(), p.test_pos.size() * sizeof(int32_t)},
       {L.nb_ptr, nb.data(), nb.size() * sizeof(int64_t)},
   };
   for (const Copy& c : copies) {
@@ -147,9 +148,10 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
   p.max_nrhs = max_nrhs;
   p.d_table = (float*)(ws + L.table);
   p.d_chunks = (int32_t*)(ws + L.chunks);
+  p.d_wg_ptr = (int32_t*)(ws + L.wg_ptr);
   p.d_pair_src = (int32_t*)(ws + L.pair_src);
   p.d_test_ptr = (int32_t*)(ws + L.test_ptr);
-  p.d_test_pos = (int32_t*)(ws + L.test_pos);
+  p.d_pair_dst = (int32_t*)(ws + L.pair_dst);
   p.d_nb_ptr = (int64_t*)(ws + L.nb_ptr);
   p.d_P = (float*)(ws + L.P);
   p.d_part = (float*)(ws + L.part);

@@ -13,6 +13,7 @@ namespace ubf {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kBlock = 256;
 
@@ -23,8 +24,8 @@ __device__ inline float wave_sum(float v) {
 }
 
 // Workgroup ids are dealt round-robin to the 8 XCDs (id % 8). Remap so that
-// XCD x works on a contiguous block of chunks; chunks are grouped by offset,
-// so each XCD's L2 only holds the operators of its own offsets. `grid` is a
+// XCD x works on a contiguous block of work; work is grouped by offset, so
+// each XCD's L2 only holds the operators of its own offsets. `grid` is a
 // multiple of 8.
 __device__ inline int xcd_chunk(int bid, int grid) {
   const int per = grid >> 3;
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(
   const float2* xb = x + (int64_t)r * nb_total + start;
   float ar = 0.f, ai = 0.f;
   if (g < G) {
+#pragma unroll 9
     for (int64_t c = g; c < nb; c += G) {
       const float2 s = Sb[c * nu + u];
       const float2 xv = xb[c];
@@ -107,90 +109,143 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(
 
 // ---------------------------------------------------------------- stage 2
 
-// Matrix-core translation, one workgroup per (chunk, rhs): a chunk is up to
-// 64 box pairs sharing one offset w. The complex product E = G_w P is done
-// as the real product
+// Matrix-core translation. A chunk is up to 128 box pairs sharing one
+// offset w; each workgroup walks a contiguous range of chunks (grouped by
+// offset, so consecutive chunks mostly reuse the operator already staged).
+// The complex product E = G_w P is done as the real product
 //   [Er; Ei] = [[Gr, -Gi], [Gi, Gr]] [Pr; Pi]
-// with M = 2*NU output rows (padded to 16-row blocks) and K = 2*KH.
-// G_w is staged in LDS as its two planes; each wavefront owns 16 pair
-// columns, holds their K values in registers, and sweeps all row blocks
-// with v_mfma_f32_16x16x4_f32. The K axis is split into four quadrants of
-// QK values, one per 16-lane group, so each lane loads a contiguous run of
-// its column and the operator read for a k-step is an immediate offset.
+// on v_mfma_f32_32x32x2_f32: M = 2*NU output rows in 32-row blocks,
+// K = 2*NU. Each wavefront owns 32 pair columns. Lane l holds column
+// l % 32 and K half h = l / 32 (h = 0: the Pr terms, h = 1: the Pi terms),
+// so a k-step of the MFMA pairs k = ks (h = 0) with k = NU + ks (h = 1) and
+// each lane's B values are one contiguous run of its box vector, kept in
+// registers. G_w sits in LDS as its two planes (rows of PITCH floats);
+// a lane reads the A values of four consecutive k-steps with one 16-byte
+// LDS read, negating -Gi with a sign flip.
 template <int NU>
 __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
     const float* __restrict__ table, const int32_t* __restrict__ chunks,
-    int n_chunks, const int32_t* __restrict__ pair_src,
-    const float* __restrict__ P, float* __restrict__ part, int64_t n_box,
-    int64_t n_pairs) {
-  constexpr int KH = (NU + 2) & ~1;
-  constexpr int QK = KH / 2;
-  constexpr int PLANE = (NU + 1) * KH;
+    const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
+    const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
+    float* __restrict__ part, int64_t n_box, int64_t n_pairs) {
+  constexpr int KH = (NU + 3) & ~3;      // padded half-length, = PITCH
+  constexpr int PLANE = NU * KH;
   constexpr int M = 2 * NU;
-  constexpr int RB = (M + 15) / 16;
+  constexpr int RB = (M + 31) / 32;      // 32-row blocks
+  constexpr int NG = NU / 4;             // full groups of 4 k-steps
   constexpr int PSTR = 2 * KH;
-  __shared__ float lds[2 * PLANE];
+  constexpr int N4 = 2 * PLANE / 4;      // float4s per operator
+  constexpr int LD = (N4 + kBlock - 1) / kBlock;
+  constexpr int NB4 = NU / 4;            // float4 loads of a lane's B run
+  __shared__ float4 lds4[N4];
+  const float* lds = reinterpret_cast<const float*>(lds4);
 
-  const int chunk = xcd_chunk(blockIdx.x, gridDim.x);
-  if (chunk >= n_chunks) return;
+  const int group = xcd_chunk(blockIdx.x, gridDim.x);
+  const int cbeg = wg_ptr[group], cend = wg_ptr[group + 1];
   const int rhs = blockIdx.y;
-  const int o = chunks[4 * chunk];
-  const int begin = chunks[4 * chunk + 1];
-  const int count = chunks[4 * chunk + 2];
-
-  const float4* g4 = reinterpret_cast<const float4*>(table + (size_t)o * 2 * PLANE);
-  float4* l4 = reinterpret_cast<float4*>(lds);
-  for (int i = threadIdx.x; i < 2 * PLANE / 4; i += kBlock) l4[i] = g4[i];
-  __syncthreads();
-
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col0 = wave * 16;
-  if (col0 >= count) return;  // no barrier follows
-  const int n = lane & 15, q = lane >> 4;
-  const int c = col0 + n;
-  const bool valid = c < count;
-  const int64_t pos = (int64_t)begin + c;
-  const int src = valid ? pair_src[pos] : 0;
-  const float* pb = P + ((int64_t)rhs * n_box + src) * PSTR + q * QK;
+  const int r = lane & 31, h = lane >> 5;
 
-  float b[QK];
-#pragma unroll
-  for (int ks = 0; ks < QK; ++ks) b[ks] = valid ? pb[ks] : 0.f;
-
-  const bool khalf_im = q >= 2;
-  const int colb = (q & 1) * QK;
-  int base[RB];
-  unsigned sgn[RB];
+  // Operator addressing: output row `row` of block rb for this lane.
+  // Er rows (< NU) read Gr for h = 0 and -Gi for h = 1; Ei rows read Gi for
+  // h = 0 and Gr for h = 1; padding rows (>= M) read row 0 (discarded).
+  int abase[RB];
+  unsigned asgn[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    const int row = rb * 16 + n;
-    const bool in_rows = row < M;
-    const bool out_im = row >= NU;
-    const int rr = in_rows ? (out_im ? row - NU : row) : NU;  // NU: zero row
-    const int plane = (khalf_im != out_im) ? 1 : 0;
-    base[rb] = plane * PLANE + rr * KH + colb;
-    sgn[rb] = (khalf_im && !out_im) ? 0x80000000u : 0u;
+    const int row = rb * 32 + r;
+    const bool er = row < NU;
+    const int rr = er ? row : (row < M ? row - NU : 0);
+    const bool im_plane = er ? (h == 1) : (row < M && h == 0);
+    abase[rb] = (im_plane ? PLANE : 0) + rr * KH;
+    asgn[rb] = (er && h == 1) ? 0x80000000u : 0u;
   }
 
-  floatx4 acc[RB];
+  int staged = -1;
+  for (int ch = cbeg; ch < cend; ++ch) {
+    const int o = chunks[4 * ch];
+    const int begin = chunks[4 * ch + 1];
+    const int count = chunks[4 * ch + 2];
+    if (o != staged) {  // uniform across the workgroup
+      __syncthreads();
+      const floatx4* g4 = reinterpret_cast<const floatx4*>(table + (size_t)o * 2 * PLANE);
+      floatx4* l4 = reinterpret_cast<floatx4*>(lds4);
+      floatx4 tmp[LD];  // every load in flight before the first LDS store
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-
+      for (int it = 0; it < LD; ++it) tmp[it] = g4[min((int)threadIdx.x + it * kBlock, N4 - 1)];
 #pragma unroll
-  for (int ks = 0; ks < QK; ++ks) {
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const float a = __uint_as_float(__float_as_uint(lds[base[rb] + ks]) ^ sgn[rb]);
-      acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks], acc[rb], 0, 0, 0);
+      for (int it = 0; it < LD; ++it) {
+        const int i = threadIdx.x + it * kBlock;
+        if (i < N4) l4[i] = tmp[it];
+      }
+      __syncthreads();
+      staged = o;
     }
-  }
+    const int col0 = wave * 32;
+    if (col0 >= count) continue;
+    const int c = col0 + r;
+    const bool valid = c < count;
+    const int64_t pos = (int64_t)begin + c;
+    const int src = valid ? pair_src[pos] : 0;
+    const int dst = valid ? pair_dst[pos] : 0;
+    const float* pb = P + ((int64_t)rhs * n_box + src) * PSTR + h * KH;
 
-  if (valid) {
-    float* out = part + ((int64_t)rhs * n_pairs + pos) * PSTR;
+    float b[NU];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int r0 = rb * 16 + q * 4;
-      if (r0 < PSTR) *reinterpret_cast<floatx4*>(out + r0) = acc[rb];
+    for (int i = 0; i < NB4; ++i) {
+      const float4 v = valid ? reinterpret_cast<const float4*>(pb)[i]
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+      b[4 * i] = v.x;
+      b[4 * i + 1] = v.y;
+      b[4 * i + 2] = v.z;
+      b[4 * i + 3] = v.w;
+    }
+#pragma unroll
+    for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = valid ? pb[ks] : 0.f;
+
+    floatx16 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      float4 a[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const float4 v = *reinterpret_cast<const float4*>(lds + abase[rb] + 4 * g);
+        a[rb] = make_float4(__uint_as_float(__float_as_uint(v.x) ^ asgn[rb]),
+                            __uint_as_float(__float_as_uint(v.y) ^ asgn[rb]),
+                            __uint_as_float(__float_as_uint(v.z) ^ asgn[rb]),
+                            __uint_as_float(__float_as_uint(v.w) ^ asgn[rb]));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb][j], b[4 * g + j], acc[rb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ks = 4 * NG; ks < NU; ++ks)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const float av = __uint_as_float(__float_as_uint(lds[abase[rb] + ks]) ^ asgn[rb]);
+        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[ks], acc[rb], 0, 0, 0);
+      }
+
+    // D layout of a 32x32 block: lane l holds column l % 32, rows
+    // 8*(v/4) + 4*(l/32) + v%4 in accumulator element v.
+    if (valid) {
+      float* out = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int r0 = rb * 32 + 8 * q4 + 4 * h;
+          if (r0 + 4 <= PSTR)
+            *reinterpret_cast<floatx4*>(out + r0) =
+                floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                        acc[rb][4 * q4 + 3]};
+        }
     }
   }
 }
@@ -200,21 +255,23 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
 // from the table through the cache.
 __global__ __launch_bounds__(kBlock) void translate_generic_kernel(
     const float* __restrict__ table, const int32_t* __restrict__ chunks,
-    const int32_t* __restrict__ pair_src, const float* __restrict__ P,
-    float* __restrict__ part, int64_t n_box, int64_t n_pairs, int nu, int kh) {
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
+    const float* __restrict__ P, float* __restrict__ part, int64_t n_box,
+    int64_t n_pairs, int nu, int kh) {
   __shared__ float pv[2 * 196];
   const int chunk = blockIdx.x;
   const int rhs = blockIdx.y;
   const int o = chunks[4 * chunk];
   const int begin = chunks[4 * chunk + 1];
   const int count = chunks[4 * chunk + 2];
-  const size_t plane = (size_t)(nu + 1) * kh;
+  const size_t plane = (size_t)nu * kh;
   const float* Gr = table + (size_t)o * 2 * plane;
   const float* Gi = Gr + plane;
   const int pstr = 2 * kh;
   for (int c = 0; c < count; ++c) {
     const int64_t pos = (int64_t)begin + c;
     const int src = pair_src[pos];
+    const int64_t dst = pair_dst[pos];
     __syncthreads();
     for (int t = threadIdx.x; t < pstr; t += kBlock)
       pv[t] = P[((int64_t)rhs * n_box + src) * pstr + t];
@@ -230,38 +287,60 @@ __global__ __launch_bounds__(kBlock) void translate_generic_kernel(
       } else {
         for (int v = 0; v < nu; ++v) s = fmaf(gr[v], pv[v], fmaf(-gi[v], pv[kh + v], s));
       }
-      part[((int64_t)rhs * n_pairs + pos) * pstr + m] = s;
+      part[((int64_t)rhs * n_pairs + dst) * pstr + m] = s;
     }
   }
 }
 
 // ---------------------------------------------------------------- stage 3
 
-// One workgroup per (test box, rhs). E_j is first gathered into LDS, either
-// as the sum of the box's partial products or from a complex input vector.
-// mode 0: identity basis (y_j = E_j); mode 1: T_j = S_j^T, one wavefront
-// per column of S_j with a wave reduction; mode 2: explicit column-major
-// T_j, one thread per output row.
+// Complex values of S_j staged in LDS per column batch (81 columns of 81,
+// plus one element of alignment slack at each end).
+constexpr int kStage = 81 * 81 + 2;
+
+// E_j into LDS (planar padded, 2*kh floats): either the sum of the box's
+// partial products (its consecutive rows of the partial buffer, read as
+// float4; the row groups' sums are combined through `scratch`) or a
+// complex input vector. Ends with a barrier.
 template <bool FROM_PARTS>
-__global__ __launch_bounds__(kBlock) void disaggregate_kernel(
-    const float* __restrict__ part, const int32_t* __restrict__ test_ptr,
-    const int32_t* __restrict__ test_pos, int64_t n_pairs,
-    const float2* __restrict__ Ein, const int64_t* __restrict__ nb_ptr,
-    const float2* __restrict__ S, const float2* __restrict__ T, int mode,
-    float2* __restrict__ y, int64_t n_box, int64_t nb_total, int nu, int kh) {
-  __shared__ float Es[2 * 192];
-  const int64_t j = blockIdx.x;
-  const int r = blockIdx.y;
+__device__ inline void gather_E(const float* __restrict__ part,
+                                const int32_t* __restrict__ test_ptr, int64_t n_pairs,
+                                const float2* __restrict__ Ein, int64_t j, int r,
+                                int64_t n_box, int nu, int kh, float4* scratch,
+                                float4* Es4) {
   const int t = threadIdx.x;
   if (FROM_PARTS) {
+    const int R4 = kh / 2;                     // float4 per partial row
+    const int H = kBlock / R4;                 // row groups
+    const int g = t % R4, h = t / R4;
     const int p0 = test_ptr[j], p1 = test_ptr[j + 1];
-    const float* pr = part + (int64_t)r * n_pairs * 2 * kh;
-    for (int m = t; m < 2 * nu; m += kBlock) {
-      float s = 0.f;
-      for (int p = p0; p < p1; ++p) s += pr[(int64_t)test_pos[p] * 2 * kh + m];
-      Es[m] = s;
+    const float4* pr = reinterpret_cast<const float4*>(part) + (int64_t)r * n_pairs * R4;
+    if (h < H) {
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+      for (int p = p0 + h; p < p1; p += H) {
+        const float4 v = pr[(int64_t)p * R4 + g];
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+        acc.w += v.w;
+      }
+      scratch[h * R4 + g] = acc;
+    }
+    __syncthreads();
+    for (int m4 = t; m4 < R4; m4 += kBlock) {
+      float4 s4 = scratch[m4];
+      for (int hh = 1; hh < H; ++hh) {
+        const float4 v = scratch[hh * R4 + m4];
+        s4.x += v.x;
+        s4.y += v.y;
+        s4.z += v.z;
+        s4.w += v.w;
+      }
+      Es4[m4] = s4;
     }
   } else {
+    float* Es = reinterpret_cast<float*>(Es4);
     for (int u = t; u < nu; u += kBlock) {
       const float2 e = Ein[((int64_t)r * n_box + j) * nu + u];
       Es[u] = e.x;
@@ -269,32 +348,78 @@ __global__ __launch_bounds__(kBlock) void disaggregate_kernel(
     }
   }
   __syncthreads();
+}
+
+// y_j[c0 + c] = sum_u S_j[u, c0 + c] E_j[u] for the ncol columns staged in
+// LDS (`shift` slots in). Four lanes per column; lane quarter q takes rows
+// u = q, q+4, ... so the lanes of a column read neighbouring words.
+__device__ inline void apply_staged(const float2* stage, int shift, int ncol,
+                                    const float* Es, int nu, float2* yb) {
+  const int t = threadIdx.x;
+  const int quarter = t & 3;
+  for (int cb = 0; cb < ncol; cb += kBlock / 4) {
+    const int c = cb + (t >> 2);
+    float sr = 0.f, si = 0.f;
+    if (c < ncol) {
+      const float2* col = stage + shift + c * nu;
+      for (int u = quarter; u < nu; u += 4) {
+        const float2 sv = col[u];
+        const float er = Es[u], ei = Es[nu + u];
+        sr = fmaf(sv.x, er, fmaf(-sv.y, ei, sr));
+        si = fmaf(sv.x, ei, fmaf(sv.y, er, si));
+      }
+    }
+    sr += __shfl_xor(sr, 1, 64);
+    si += __shfl_xor(si, 1, 64);
+    sr += __shfl_xor(sr, 2, 64);
+    si += __shfl_xor(si, 2, 64);
+    if (c < ncol && quarter == 0) yb[c] = make_float2(sr, si);
+  }
+}
+
+// One workgroup per (test box, rhs): E_j (gather_E), then y_j = T_j E_j.
+// mode 0: identity basis (y_j = E_j). mode 1: T_j = S_j^T; S_j is read in
+// batches of CB columns, staged in LDS and applied by apply_staged. In a
+// batch, slots (float4 = two complex values from the 16-byte aligned
+// address at or below the batch start) whose halves both belong to the
+// batch are read with indices clamped into that range, so the loads carry
+// no branches and all are in flight before any is used; the at most two
+// half slots at the ends are read as float2. The first batch is issued
+// before E_j is gathered, overlapping the two streams. mode 2: explicit
+// column-major T_j, one thread per output row.
+// LDS (about 54 KB) allows three workgroups per compute unit; the bound
+// lets the compiler keep a whole staged batch in registers.
+template <bool FROM_PARTS>
+__global__ __launch_bounds__(kBlock, 3) void disaggregate_kernel(
+    const float* __restrict__ part, const int32_t* __restrict__ test_ptr,
+    int64_t n_pairs, const float2* __restrict__ Ein, const int64_t* __restrict__ nb_ptr,
+    const float2* __restrict__ S, const float2* __restrict__ T, int mode,
+    float2* __restrict__ y, int64_t n_box, int64_t nb_total, int nu, int kh) {
+  constexpr int LD = ((kStage + 1) / 2 + kBlock - 1) / kBlock;
+  __shared__ float4 Es4[98];                  // E_j, planar padded (2*kh floats)
+  __shared__ float4 stage4[(kStage + 1) / 2];  // S_j batch, or gather scratch
+  const float* Es = reinterpret_cast<const float*>(Es4);
+  const float2* stage = reinterpret_cast<const float2*>(stage4);
+  const int64_t j = blockIdx.x;
+  const int r = blockIdx.y;
+  const int t = threadIdx.x;
   float2* yb = y + (int64_t)r * nb_total;
+
   if (mode == 0) {
+    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
+                         kh, stage4, Es4);
     for (int u = t; u < nu; u += kBlock) yb[j * nu + u] = make_float2(Es[u], Es[nu + u]);
     return;
   }
   const int64_t start = nb_ptr[j];
   const int64_t nb = nb_ptr[j + 1] - start;
-  if (mode == 1) {
-    const int wave = t >> 6, lane = t & 63;
-    for (int64_t c = wave; c < nb; c += kBlock / 64) {
-      const float2* col = S + (start + c) * nu;
-      float sr = 0.f, si = 0.f;
-      for (int u = lane; u < nu; u += 64) {
-        const float2 s = col[u];
-        const float er = Es[u], ei = Es[nu + u];
-        sr = fmaf(s.x, er, fmaf(-s.y, ei, sr));
-        si = fmaf(s.x, ei, fmaf(s.y, er, si));
-      }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
-      if (lane == 0) yb[start + c] = make_float2(sr, si);
-    }
-  } else {
+  if (mode == 2) {
+    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
+                         kh, stage4, Es4);
     const float2* Tb = T + start * nu;
     for (int64_t c = t; c < nb; c += kBlock) {
       float sr = 0.f, si = 0.f;
+#pragma unroll 9
       for (int u = 0; u < nu; ++u) {
         const float2 v = Tb[c + nb * u];
         const float er = Es[u], ei = Es[nu + u];
@@ -303,6 +428,46 @@ __global__ __launch_bounds__(kBlock) void disaggregate_kernel(
       }
       yb[start + c] = make_float2(sr, si);
     }
+    return;
+  }
+
+  // mode 1
+  const int CB = (kStage - 2) / nu;            // columns per batch
+  if (nb <= 0) {
+    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
+                         kh, stage4, Es4);
+    return;
+  }
+  for (int64_t c0 = 0; c0 < nb; c0 += CB) {
+    const int ncol = (int)min((int64_t)CB, nb - c0);
+    const float2* blk = S + (start + c0) * nu;
+    const int shift = (reinterpret_cast<uintptr_t>(blk) & 15) ? 1 : 0;
+    const int lim = ncol * nu + shift;
+    const int n4 = (lim + 1) / 2;
+    const int lo = shift;
+    const int hi = (lim & 1) ? n4 - 2 : n4 - 1;
+    const float2* s2 = blk - shift;
+    const floatx4* s4 = reinterpret_cast<const floatx4*>(s2);
+    floatx4 tmp[LD];
+#pragma unroll
+    for (int it = 0; it < LD; ++it) tmp[it] = s4[min(max(t + it * kBlock, lo), hi)];
+    const float2 edge0 = s2[shift ? 1 : 2 * lo];
+    const float2 edge1 = s2[(lim & 1) ? 2 * (n4 - 1) : 2 * hi];
+    if (c0 == 0)
+      gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
+                           kh, stage4, Es4);
+    else
+      __syncthreads();  // previous batch fully consumed
+    floatx4* stagev = reinterpret_cast<floatx4*>(stage4);
+#pragma unroll
+    for (int it = 0; it < LD; ++it) {
+      const int i = t + it * kBlock;
+      if (i >= lo && i <= hi) stagev[i] = tmp[it];
+    }
+    if (t == 0 && shift) stagev[0] = floatx4{0.f, 0.f, edge0.x, edge0.y};
+    if (t == 1 && (lim & 1)) stagev[n4 - 1] = floatx4{edge1.x, edge1.y, 0.f, 0.f};
+    __syncthreads();
+    apply_staged(stage, shift, ncol, Es, nu, yb + start + c0);
   }
 }
 
@@ -344,27 +509,27 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
   const int nch = (int)p.n_chunks();
   if (nch == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid8((unsigned)((nch + 7) / 8 * 8), nrhs);
+  const dim3 groups((unsigned)p.n_groups(), nrhs);
   switch (p.nu) {
     case 81:
-      hipLaunchKernelGGL(translate_mfma_kernel<81>, grid8, dim3(kBlock), 0, s,
-                         p.d_table, p.d_chunks, nch, p.d_pair_src, P, part,
+      hipLaunchKernelGGL(translate_mfma_kernel<81>, groups, dim3(kBlock), 0, s,
+                         p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
                          p.n_box, p.n_pairs());
       break;
     case 24:
-      hipLaunchKernelGGL(translate_mfma_kernel<24>, grid8, dim3(kBlock), 0, s,
-                         p.d_table, p.d_chunks, nch, p.d_pair_src, P, part,
+      hipLaunchKernelGGL(translate_mfma_kernel<24>, groups, dim3(kBlock), 0, s,
+                         p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
                          p.n_box, p.n_pairs());
       break;
     case 3:
-      hipLaunchKernelGGL(translate_mfma_kernel<3>, grid8, dim3(kBlock), 0, s,
-                         p.d_table, p.d_chunks, nch, p.d_pair_src, P, part,
+      hipLaunchKernelGGL(translate_mfma_kernel<3>, groups, dim3(kBlock), 0, s,
+                         p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
                          p.n_box, p.n_pairs());
       break;
     default:
       hipLaunchKernelGGL(translate_generic_kernel, dim3((unsigned)nch, nrhs),
                          dim3(kBlock), 0, s, p.d_table, p.d_chunks, p.d_pair_src,
-                         P, part, p.n_box, p.n_pairs(), p.nu, p.kh);
+                         p.d_pair_dst, P, part, p.n_box, p.n_pairs(), p.nu, p.kh);
   }
   return (int)hipGetLastError();
 }
@@ -378,12 +543,12 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
   hipStream_t s = (hipStream_t)stream;
   if (from_parts)
     hipLaunchKernelGGL(disaggregate_kernel<true>, grid, dim3(kBlock), 0, s, part,
-                       p.d_test_ptr, p.d_test_pos, p.n_pairs(), (const float2*)E,
+                       p.d_test_ptr, p.n_pairs(), (const float2*)E,
                        p.d_nb_ptr, (const float2*)p.d_S, (const float2*)p.d_T, mode,
                        (float2*)y, p.n_box, nb_total, p.nu, p.kh);
   else
     hipLaunchKernelGGL(disaggregate_kernel<false>, grid, dim3(kBlock), 0, s, part,
-                       p.d_test_ptr, p.d_test_pos, p.n_pairs(), (const float2*)E,
+                       p.d_test_ptr, p.n_pairs(), (const float2*)E,
                        p.d_nb_ptr, (const float2*)p.d_S, (const float2*)p.d_T, mode,
                        (float2*)y, p.n_box, nb_total, p.nu, p.kh);
   return (int)hipGetLastError();

@@ -132,9 +132,10 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   };
   L.table = take(p.table.size() * sizeof(float));
   L.chunks = take(p.chunks.size() * sizeof(int32_t));
+  L.wg_ptr = take(p.wg_ptr.size() * sizeof(int32_t));
   L.pair_src = take(p.pair_src.size() * sizeof(int32_t));
+  L.pair_dst = take(p.pair_dst.size() * sizeof(int32_t));
   L.test_ptr = take(p.test_ptr.size() * sizeof(int32_t));
-  L.test_pos = take(p.test_pos.size() * sizeof(int32_t));
   L.nb_ptr = take((size_t)(p.n_box + 1) * sizeof(int64_t));
   L.P = take((size_t)max_nrhs * p.n_box * p.pstride() * sizeof(float));
   L.part = take((size_t)max_nrhs * p.n_pairs() * p.pstride() * sizeof(float));
@@ -214,7 +215,7 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   std::sort(uniq.begin(), uniq.end());
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
   const int64_t n_off = (int64_t)uniq.size();
-  const double table_bytes = (double)n_off * 2.0 * (P.nu + 1) * P.kh * sizeof(float);
+  const double table_bytes = (double)n_off * 2.0 * P.nu * P.kh * sizeof(float);
   if (table_bytes > kMaxTableBytes) return "operator table would exceed 16 GiB";
   P.offsets.resize(3 * n_off);
   for (int64_t o = 0; o < n_off; ++o)
@@ -246,6 +247,10 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   std::vector<int32_t> tfill(P.test_ptr.begin(), P.test_ptr.end() - 1);
   P.test_pos.resize(np);
   for (int64_t p = 0; p < np; ++p) P.test_pos[tfill[P.pair_test[p]]++] = (int32_t)p;
+  // Partial products are written at their test-major position, so the
+  // pairs of one test box occupy consecutive rows.
+  P.pair_dst.resize(np);
+  for (int64_t q = 0; q < np; ++q) P.pair_dst[P.test_pos[q]] = (int32_t)q;
 
   // Work units: up to kChunk consecutive pairs of one offset.
   P.chunks.clear();
@@ -256,6 +261,28 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
       P.chunks.push_back((int32_t)std::min<int64_t>(kChunk, P.off_ptr[o + 1] - s));
       P.chunks.push_back(0);
     }
+
+  // Contiguous chunk ranges per translation workgroup, balanced by chunk
+  // count: the four wavefronts of a group work on one chunk at a time, so a
+  // group's time is its number of chunks whatever their fill. The group
+  // count is a multiple of 8 (one share per XCD); trailing groups may get
+  // empty ranges.
+  {
+    const int64_t nch = P.n_chunks();
+    int64_t groups = std::min<int64_t>(kTranslateGroups, std::max<int64_t>(nch, 1));
+    groups = (groups + 7) / 8 * 8;
+    std::vector<int64_t> cost(nch + 1, 0);
+    for (int64_t c = 0; c < nch; ++c) cost[c + 1] = cost[c] + 1;
+    const int64_t total = cost[nch];
+    P.wg_ptr.assign(groups + 1, (int32_t)nch);
+    P.wg_ptr[0] = 0;
+    int64_t c = 0;
+    for (int64_t g = 1; g < groups; ++g) {
+      const int64_t target = (total * g + groups - 1) / groups;
+      while (c < nch && cost[c] < target) ++c;
+      P.wg_ptr[g] = (int32_t)c;
+    }
+  }
 
   // Orbits under the 48 signed permutations: key = sorted |w|.
   std::vector<std::array<int32_t, 3>> keys(n_off);

@@ -11,12 +11,15 @@
 
 namespace ubf {
 
-// Columns (box pairs) per translation work unit: four wavefronts of 16.
-constexpr int kChunk = 64;
+// Columns (box pairs) per translation work unit: four wavefronts of 32.
+constexpr int kChunk = 128;
+// Translation workgroups: two resident per compute unit on 256 CUs.
+constexpr int kTranslateGroups = 512;
 
-// Padded half-length of a planar box vector: N_u + 1 rounded up to even.
-// A box vector is stored as [re(N_u), 0 pad | im(N_u), 0 pad], 2*kh floats.
-inline int half_len(int nu) { return (nu + 2) & ~1; }
+// Padded half-length of a planar box vector: N_u rounded up to a multiple
+// of 4. A box vector is stored as [re(N_u), 0 pad | im(N_u), 0 pad], 2*kh
+// floats, so both halves start 16-byte aligned.
+inline int half_len(int nu) { return (nu + 3) & ~3; }
 
 // Free-space dyadic Green's function of Eq. (5)-(6), FP64, time
 // convention exp(+j omega t): D(R) = psi(R) { I (1 - j/kR - 1/(kR)^2)
@@ -47,17 +50,20 @@ struct Plan {
   std::vector<int32_t> pair_off;   // n_pairs
   std::vector<int32_t> test_ptr;   // n_box + 1: pairs of each test box ...
   std::vector<int32_t> test_pos;   // ... as positions in the grouped order
+  std::vector<int32_t> pair_dst;   // grouped position -> test-major position
   std::vector<int32_t> chunks;     // 4 per chunk: offset, begin, count, 0
+  std::vector<int32_t> wg_ptr;     // chunk range of each translation workgroup
   int32_t n_orbits = 0;
 
-  // Operator table image: per offset two planes (re, im) of (nu+1) rows of
-  // kh floats; row nu and columns >= nu are zero.
+  // Operator table image: per offset two planes (re, im) of nu rows of kh
+  // floats; columns >= nu are zero.
   std::vector<float> table;
 
   int64_t n_pairs() const { return (int64_t)pair_src.size(); }
   int32_t n_off() const { return (int32_t)(offsets.size() / 3); }
   int64_t n_chunks() const { return (int64_t)(chunks.size() / 4); }
-  size_t plane_floats() const { return (size_t)(nu + 1) * kh; }
+  int32_t n_groups() const { return (int32_t)wg_ptr.size() - 1; }
+  size_t plane_floats() const { return (size_t)nu * kh; }
   size_t op_floats() const { return 2 * plane_floats(); }
   int pstride() const { return 2 * kh; }
 
@@ -68,9 +74,10 @@ struct Plan {
   // Device pointers into the workspace.
   float* d_table = nullptr;
   int32_t* d_chunks = nullptr;
+  int32_t* d_wg_ptr = nullptr;
   int32_t* d_pair_src = nullptr;
   int32_t* d_test_ptr = nullptr;
-  int32_t* d_test_pos = nullptr;
+  int32_t* d_pair_dst = nullptr;
   int64_t* d_nb_ptr = nullptr;
   float* d_P = nullptr;
   float* d_part = nullptr;
@@ -87,7 +94,7 @@ struct Plan {
 
 // Workspace layout, in bytes from the workspace start.
 struct Layout {
-  size_t table, chunks, pair_src, test_ptr, test_pos, nb_ptr, P, part, total;
+  size_t table, chunks, wg_ptr, pair_src, pair_dst, test_ptr, nb_ptr, P, part, total;
 };
 Layout workspace_layout(const Plan& p, int32_t max_nrhs);
 

@@ -114,7 +114,7 @@ def test_plan_far_set_matches_oracle(cfg):
         for oo in np.unique(o)[:20]:
             assert np.all(np.diff(t[o == oo]) > 0)
         # the work partition covers every pair once
-        assert info["n_chunks"] >= -(-len(j) // 64)
+        assert info["n_chunks"] >= -(-len(j) // 128)
     finally:
         U.plan_destroy(plan)
 
