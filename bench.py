@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing "
+                         "(reference kernel for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -115,6 +118,14 @@ def main():
     X = torch.from_numpy(W.complex_normal((n_vec, nrhs, nb_total), seed=1000)).to(dev)
     Y = torch.empty((nrhs, nb_total), dtype=torch.complex64, device=dev)
     stream = torch.cuda.current_stream().cuda_stream
+
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for s in range(args.warmup):
         U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)

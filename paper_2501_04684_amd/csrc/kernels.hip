@@ -127,11 +127,15 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
     const float* __restrict__ table, const int32_t* __restrict__ chunks,
     const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
     const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
-    float* __restrict__ part, int64_t n_box, int64_t n_pairs) {
+    float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row) {
   constexpr int KH = (NU + 3) & ~3;      // padded half-length, = PITCH
   constexpr int PLANE = NU * KH;
   constexpr int M = 2 * NU;
-  constexpr int RB = (M + 31) / 32;      // 32-row blocks
+  // Full 32-row blocks run on the matrix cores; up to 4 leftover rows (2 for
+  // N_u = 81: rows 160, 161) are accumulated on the VALU instead of a
+  // mostly empty extra block. Larger remainders take a padded block.
+  constexpr int LRV = (M % 32 <= 4) ? M % 32 : 0;   // VALU rows
+  constexpr int RB = (M - LRV + 31) / 32;            // MFMA row blocks
   constexpr int NG = NU / 4;             // full groups of 4 k-steps
   constexpr int PSTR = 2 * KH;
   constexpr int N4 = 2 * PLANE / 4;      // float4s per operator
@@ -149,11 +153,12 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
   // Operator addressing: output row `row` of block rb for this lane.
   // Er rows (< NU) read Gr for h = 0 and -Gi for h = 1; Ei rows read Gi for
   // h = 0 and Gr for h = 1; padding rows (>= M) read row 0 (discarded).
-  int abase[RB];
-  unsigned asgn[RB];
+  int abase[RB + LRV];
+  unsigned asgn[RB + LRV];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
-    const int row = rb * 32 + r;
+  for (int rb = 0; rb < RB + LRV; ++rb) {
+    // MFMA blocks: this lane's row of block rb; VALU rows: row 32*RB + i.
+    const int row = rb < RB ? rb * 32 + r : 32 * RB + (rb - RB);
     const bool er = row < NU;
     const int rr = er ? row : (row < M ? row - NU : 0);
     const bool im_plane = er ? (h == 1) : (row < M && h == 0);
@@ -161,14 +166,47 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
     asgn[rb] = (er && h == 1) ? 0x80000000u : 0u;
   }
 
+  if (cbeg >= cend) return;
+  const int col0 = wave * 32;
+  const int64_t last = n_pairs - 1;
+
+  // Every global access below is unconditional, so the in-order counter of
+  // outstanding vector memory operations stays exact and waits are only as
+  // deep as needed: a lane past its chunk's count reads the column of a
+  // clamped (valid) pair and stores into the spare row `trash_row`; a B
+  // column only feeds its own output column, so nothing else is affected.
+  // Pair indices are fetched two chunks ahead (before the stores that lie
+  // between), B values one chunk ahead: while k-group g of the current
+  // chunk is multiplied, b's group g is refilled for the next chunk.
+  int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
+  const bool has1 = cbeg + 1 < cend;
+  int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
+  int b1 = has1 ? chunks[4 * (cbeg + 1) + 1] : 0;
+  int n1 = has1 ? chunks[4 * (cbeg + 1) + 2] : 0;
+  int64_t i0 = min((int64_t)b0 + col0 + r, last), i1 = min((int64_t)b1 + col0 + r, last);
+  int src0 = pair_src[i0], dst0 = pair_dst[i0];
+  int src1 = pair_src[i1], dst1 = pair_dst[i1];
+
+  float b[NU];
+  {
+    const float* pb = P + ((int64_t)rhs * n_box + src0) * PSTR + h * KH;
+#pragma unroll
+    for (int i = 0; i < NB4; ++i) {
+      const floatx4 v = reinterpret_cast<const floatx4*>(pb)[i];
+      b[4 * i] = v[0];
+      b[4 * i + 1] = v[1];
+      b[4 * i + 2] = v[2];
+      b[4 * i + 3] = v[3];
+    }
+#pragma unroll
+    for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb[ks];
+  }
+
   int staged = -1;
   for (int ch = cbeg; ch < cend; ++ch) {
-    const int o = chunks[4 * ch];
-    const int begin = chunks[4 * ch + 1];
-    const int count = chunks[4 * ch + 2];
-    if (o != staged) {  // uniform across the workgroup
+    if (o0 != staged) {  // uniform across the workgroup
       __syncthreads();
-      const floatx4* g4 = reinterpret_cast<const floatx4*>(table + (size_t)o * 2 * PLANE);
+      const floatx4* g4 = reinterpret_cast<const floatx4*>(table + (size_t)o0 * 2 * PLANE);
       floatx4* l4 = reinterpret_cast<floatx4*>(lds4);
       floatx4 tmp[LD];  // every load in flight before the first LDS store
 #pragma unroll
@@ -179,74 +217,115 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
         if (i < N4) l4[i] = tmp[it];
       }
       __syncthreads();
-      staged = o;
+      staged = o0;
     }
-    const int col0 = wave * 32;
-    if (col0 >= count) continue;
-    const int c = col0 + r;
-    const bool valid = c < count;
-    const int64_t pos = (int64_t)begin + c;
-    const int src = valid ? pair_src[pos] : 0;
-    const int dst = valid ? pair_dst[pos] : 0;
-    const float* pb = P + ((int64_t)rhs * n_box + src) * PSTR + h * KH;
+    const bool has2 = ch + 2 < cend;
+    const int o2 = has2 ? chunks[4 * (ch + 2)] : o1;
+    const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
+    const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
+    const int64_t i2 = min((int64_t)b2 + col0 + r, last);
+    const float* pb1 = P + ((int64_t)rhs * n_box + src1) * PSTR + h * KH;
+    int src2, dst2;
 
-    float b[NU];
+    if (col0 < n0) {  // wave-uniform
+      floatx16 acc[RB];
+      float vacc[LRV > 0 ? LRV : 1];
 #pragma unroll
-    for (int i = 0; i < NB4; ++i) {
-      const float4 v = valid ? reinterpret_cast<const float4*>(pb)[i]
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
-      b[4 * i] = v.x;
-      b[4 * i + 1] = v.y;
-      b[4 * i + 2] = v.z;
-      b[4 * i + 3] = v.w;
-    }
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
 #pragma unroll
-    for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = valid ? pb[ks] : 0.f;
-
-    floatx16 acc[RB];
+      for (int i = 0; i < LRV; ++i) vacc[i] = 0.f;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
-
+      for (int g = 0; g < NG; ++g) {
+        float4 a[RB + LRV];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      float4 a[RB];
+        for (int rb = 0; rb < RB + LRV; ++rb) {
+          const float4 v = *reinterpret_cast<const float4*>(lds + abase[rb] + 4 * g);
+          a[rb] = make_float4(__uint_as_float(__float_as_uint(v.x) ^ asgn[rb]),
+                              __uint_as_float(__float_as_uint(v.y) ^ asgn[rb]),
+                              __uint_as_float(__float_as_uint(v.z) ^ asgn[rb]),
+                              __uint_as_float(__float_as_uint(v.w) ^ asgn[rb]));
+        }
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const float4 v = *reinterpret_cast<const float4*>(lds + abase[rb] + 4 * g);
-        a[rb] = make_float4(__uint_as_float(__float_as_uint(v.x) ^ asgn[rb]),
-                            __uint_as_float(__float_as_uint(v.y) ^ asgn[rb]),
-                            __uint_as_float(__float_as_uint(v.z) ^ asgn[rb]),
-                            __uint_as_float(__float_as_uint(v.w) ^ asgn[rb]));
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb][jj], b[4 * g + jj], acc[rb], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < LRV; ++i) {
+          vacc[i] = fmaf(a[RB + i].x, b[4 * g], vacc[i]);
+          vacc[i] = fmaf(a[RB + i].y, b[4 * g + 1], vacc[i]);
+          vacc[i] = fmaf(a[RB + i].z, b[4 * g + 2], vacc[i]);
+          vacc[i] = fmaf(a[RB + i].w, b[4 * g + 3], vacc[i]);
+        }
+        const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[g];  // next chunk
+        b[4 * g] = v[0];
+        b[4 * g + 1] = v[1];
+        b[4 * g + 2] = v[2];
+        b[4 * g + 3] = v[3];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int ks = 4 * NG; ks < NU; ++ks) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb][j], b[4 * g + j], acc[rb], 0, 0, 0);
-    }
+        for (int rb = 0; rb < RB; ++rb) {
+          const float av = __uint_as_float(__float_as_uint(lds[abase[rb] + ks]) ^ asgn[rb]);
+          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[ks], acc[rb], 0, 0, 0);
+        }
 #pragma unroll
-    for (int ks = 4 * NG; ks < NU; ++ks)
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const float av = __uint_as_float(__float_as_uint(lds[abase[rb] + ks]) ^ asgn[rb]);
-        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[ks], acc[rb], 0, 0, 0);
+        for (int i = 0; i < LRV; ++i) {
+          const float av = __uint_as_float(__float_as_uint(lds[abase[RB + i] + ks]) ^ asgn[RB + i]);
+          vacc[i] = fmaf(av, b[ks], vacc[i]);
+        }
+        b[ks] = pb1[ks];
       }
+      // VALU rows: add the other K half (lane l +- 32 holds it).
+#pragma unroll
+      for (int i = 0; i < LRV; ++i) vacc[i] += __shfl_xor(vacc[i], 32, 64);
+      src2 = pair_src[i2];
+      dst2 = pair_dst[i2];
 
-    // D layout of a 32x32 block: lane l holds column l % 32, rows
-    // 8*(v/4) + 4*(l/32) + v%4 in accumulator element v.
-    if (valid) {
-      float* out = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
+      // D layout of a 32x32 block: lane l holds column l % 32, rows
+      // 8*(v/4) + 4*(l/32) + v%4 in accumulator element v.
+      const int64_t row = (col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
+      float* out = part + row * PSTR;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int r0 = rb * 32 + 8 * q4 + 4 * h;
-          if (r0 + 4 <= PSTR)
+          if (rb * 32 + 8 * q4 + 8 <= PSTR)  // same for both halves h
             *reinterpret_cast<floatx4*>(out + r0) =
                 floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
                         acc[rb][4 * q4 + 3]};
         }
+      if (LRV > 0) {
+        // rows 32*RB .. 32*RB+LRV-1; lanes of both halves hold the sums,
+        // half h writes the even/odd pair starting at 2*h
+#pragma unroll
+        for (int i = 0; i < LRV; i += 2) {
+          if (i + 1 < LRV) {
+            if (2 * h == i % 4)
+              *reinterpret_cast<float2*>(out + 32 * RB + i) = make_float2(vacc[i], vacc[i + 1]);
+          } else if (h == 0) {
+            out[32 * RB + i] = vacc[i];
+          }
+        }
+      }
+    } else {  // no column of this chunk for this wavefront: fetch the next
+#pragma unroll
+      for (int i = 0; i < NB4; ++i) {
+        const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[i];
+        b[4 * i] = v[0];
+        b[4 * i + 1] = v[1];
+        b[4 * i + 2] = v[2];
+        b[4 * i + 3] = v[3];
+      }
+#pragma unroll
+      for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb1[ks];
+      src2 = pair_src[i2];
+      dst2 = pair_dst[i2];
     }
+    o0 = o1; n0 = n1; dst0 = dst1;
+    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;
   }
 }
 
@@ -317,7 +396,7 @@ __device__ inline void gather_E(const float* __restrict__ part,
     const float4* pr = reinterpret_cast<const float4*>(part) + (int64_t)r * n_pairs * R4;
     if (h < H) {
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll 8
+#pragma unroll 4
       for (int p = p0 + h; p < p1; p += H) {
         const float4 v = pr[(int64_t)p * R4 + g];
         acc.x += v.x;
@@ -351,29 +430,37 @@ __device__ inline void gather_E(const float* __restrict__ part,
 }
 
 // y_j[c0 + c] = sum_u S_j[u, c0 + c] E_j[u] for the ncol columns staged in
-// LDS (`shift` slots in). Four lanes per column; lane quarter q takes rows
-// u = q, q+4, ... so the lanes of a column read neighbouring words.
+// LDS (`shift` slots in). A wavefront takes 16 columns per pass; lane l
+// handles column l % 16 and rows u = q, q + 4, q + 8, ... with q = l / 16,
+// so the 16 lanes of a quarter read 16 different columns (conflict-free
+// 8-byte LDS reads) and the rows of E_j a lane needs are fixed: they are
+// held in registers (er/ei, EQ >= ceil(nu / 4) rows per lane).
+template <int EQ>
 __device__ inline void apply_staged(const float2* stage, int shift, int ncol,
-                                    const float* Es, int nu, float2* yb) {
+                                    const float (&er)[EQ], const float (&ei)[EQ],
+                                    int nu, float2* yb) {
   const int t = threadIdx.x;
-  const int quarter = t & 3;
-  for (int cb = 0; cb < ncol; cb += kBlock / 4) {
-    const int c = cb + (t >> 2);
+  const int lane = t & 63, wave = t >> 6;
+  const int q = lane >> 4;
+  for (int cb = wave * 16; cb < ncol; cb += kBlock / 4) {
+    const int c = cb + (lane & 15);
     float sr = 0.f, si = 0.f;
     if (c < ncol) {
-      const float2* col = stage + shift + c * nu;
-      for (int u = quarter; u < nu; u += 4) {
-        const float2 sv = col[u];
-        const float er = Es[u], ei = Es[nu + u];
-        sr = fmaf(sv.x, er, fmaf(-sv.y, ei, sr));
-        si = fmaf(sv.x, ei, fmaf(sv.y, er, si));
+      const float2* col = stage + shift + c * nu + q;
+#pragma unroll
+      for (int i = 0; i < EQ; ++i) {
+        if (q + 4 * i < nu) {
+          const float2 sv = col[4 * i];
+          sr = fmaf(sv.x, er[i], fmaf(-sv.y, ei[i], sr));
+          si = fmaf(sv.x, ei[i], fmaf(sv.y, er[i], si));
+        }
       }
     }
-    sr += __shfl_xor(sr, 1, 64);
-    si += __shfl_xor(si, 1, 64);
-    sr += __shfl_xor(sr, 2, 64);
-    si += __shfl_xor(si, 2, 64);
-    if (c < ncol && quarter == 0) yb[c] = make_float2(sr, si);
+    sr += __shfl_xor(sr, 16, 64);
+    si += __shfl_xor(si, 16, 64);
+    sr += __shfl_xor(sr, 32, 64);
+    si += __shfl_xor(si, 32, 64);
+    if (c < ncol && q == 0) yb[c] = make_float2(sr, si);
   }
 }
 
@@ -388,9 +475,10 @@ __device__ inline void apply_staged(const float2* stage, int shift, int ncol,
 // before E_j is gathered, overlapping the two streams. mode 2: explicit
 // column-major T_j, one thread per output row.
 // LDS (about 54 KB) allows three workgroups per compute unit; the bound
-// lets the compiler keep a whole staged batch in registers.
-template <bool FROM_PARTS>
-__global__ __launch_bounds__(kBlock, 3) void disaggregate_kernel(
+// lets the compiler keep a whole staged batch in registers. EQ is the
+// number of E_j rows each lane keeps (ceil(nu / 4) at most).
+template <bool FROM_PARTS, int EQ>
+__global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
     const float* __restrict__ part, const int32_t* __restrict__ test_ptr,
     int64_t n_pairs, const float2* __restrict__ Ein, const int64_t* __restrict__ nb_ptr,
     const float2* __restrict__ S, const float2* __restrict__ T, int mode,
@@ -438,9 +526,10 @@ __global__ __launch_bounds__(kBlock, 3) void disaggregate_kernel(
                          kh, stage4, Es4);
     return;
   }
-  for (int64_t c0 = 0; c0 < nb; c0 += CB) {
-    const int ncol = (int)min((int64_t)CB, nb - c0);
-    const float2* blk = S + (start + c0) * nu;
+  // First batch: its loads are in flight while E_j is gathered.
+  {
+    const int ncol = (int)min((int64_t)CB, nb);
+    const float2* blk = S + start * nu;
     const int shift = (reinterpret_cast<uintptr_t>(blk) & 15) ? 1 : 0;
     const int lim = ncol * nu + shift;
     const int n4 = (lim + 1) / 2;
@@ -453,11 +542,7 @@ __global__ __launch_bounds__(kBlock, 3) void disaggregate_kernel(
     for (int it = 0; it < LD; ++it) tmp[it] = s4[min(max(t + it * kBlock, lo), hi)];
     const float2 edge0 = s2[shift ? 1 : 2 * lo];
     const float2 edge1 = s2[(lim & 1) ? 2 * (n4 - 1) : 2 * hi];
-    if (c0 == 0)
-      gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
-                           kh, stage4, Es4);
-    else
-      __syncthreads();  // previous batch fully consumed
+    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu, kh, stage4, Es4);
     floatx4* stagev = reinterpret_cast<floatx4*>(stage4);
 #pragma unroll
     for (int it = 0; it < LD; ++it) {
@@ -466,8 +551,59 @@ __global__ __launch_bounds__(kBlock, 3) void disaggregate_kernel(
     }
     if (t == 0 && shift) stagev[0] = floatx4{0.f, 0.f, edge0.x, edge0.y};
     if (t == 1 && (lim & 1)) stagev[n4 - 1] = floatx4{edge1.x, edge1.y, 0.f, 0.f};
+    float er[EQ], ei[EQ];  // this lane's rows of E_j (see apply_staged)
+    const int q = (t & 63) >> 4;
+#pragma unroll
+    for (int i = 0; i < EQ; ++i) {
+      const int u = min(q + 4 * i, nu - 1);
+      er[i] = Es[u];
+      ei[i] = Es[nu + u];
+    }
     __syncthreads();
-    apply_staged(stage, shift, ncol, Es, nu, yb + start + c0);
+    apply_staged<EQ>(stage, shift, ncol, er, ei, nu, yb + start);
+  }
+  // Boxes with more than CB functions: further batches are copied straight
+  // into LDS and applied with E_j read from LDS (rare).
+  for (int64_t c0 = CB; c0 < nb; c0 += CB) {
+    __syncthreads();  // previous batch fully consumed
+    const int ncol = (int)min((int64_t)CB, nb - c0);
+    const float2* blk = S + (start + c0) * nu;
+    const int shift = (reinterpret_cast<uintptr_t>(blk) & 15) ? 1 : 0;
+    const int lim = ncol * nu + shift;
+    const int n4 = (lim + 1) / 2;
+    const int lo = shift;
+    const int hi = (lim & 1) ? n4 - 2 : n4 - 1;
+    const float2* s2 = blk - shift;
+    const floatx4* s4 = reinterpret_cast<const floatx4*>(s2);
+    floatx4* stagev = reinterpret_cast<floatx4*>(stage4);
+    for (int i = lo + t; i <= hi; i += kBlock) stagev[i] = s4[i];
+    if (t == 0 && shift) {
+      const float2 v = s2[1];
+      stagev[0] = floatx4{0.f, 0.f, v.x, v.y};
+    }
+    if (t == 1 && (lim & 1)) {
+      const float2 v = s2[2 * (n4 - 1)];
+      stagev[n4 - 1] = floatx4{v.x, v.y, 0.f, 0.f};
+    }
+    __syncthreads();
+    const int quarter = t & 3;
+    for (int cb = 0; cb < ncol; cb += kBlock / 4) {
+      const int c = cb + (t >> 2);
+      float sr = 0.f, si = 0.f;
+      if (c < ncol) {
+        const float2* col = stage + shift + c * nu;
+        for (int u = quarter; u < nu; u += 4) {
+          const float2 sv = col[u];
+          sr = fmaf(sv.x, Es[u], fmaf(-sv.y, Es[nu + u], sr));
+          si = fmaf(sv.x, Es[nu + u], fmaf(sv.y, Es[u], si));
+        }
+      }
+      sr += __shfl_xor(sr, 1, 64);
+      si += __shfl_xor(si, 1, 64);
+      sr += __shfl_xor(sr, 2, 64);
+      si += __shfl_xor(si, 2, 64);
+      if (c < ncol && quarter == 0) yb[start + c0 + c] = make_float2(sr, si);
+    }
   }
 }
 
@@ -514,17 +650,17 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
     case 81:
       hipLaunchKernelGGL(translate_mfma_kernel<81>, groups, dim3(kBlock), 0, s,
                          p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs());
+                         p.n_box, p.n_pairs(), (int64_t)p.max_nrhs * p.n_pairs());
       break;
     case 24:
       hipLaunchKernelGGL(translate_mfma_kernel<24>, groups, dim3(kBlock), 0, s,
                          p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs());
+                         p.n_box, p.n_pairs(), (int64_t)p.max_nrhs * p.n_pairs());
       break;
     case 3:
       hipLaunchKernelGGL(translate_mfma_kernel<3>, groups, dim3(kBlock), 0, s,
                          p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs());
+                         p.n_box, p.n_pairs(), (int64_t)p.max_nrhs * p.n_pairs());
       break;
     default:
       hipLaunchKernelGGL(translate_generic_kernel, dim3((unsigned)nch, nrhs),
@@ -541,16 +677,18 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
   const int64_t nb_total = mode == 0 ? p.n_box * (int64_t)p.nu : p.nb_total();
   const dim3 grid((unsigned)p.n_box, nrhs);
   hipStream_t s = (hipStream_t)stream;
-  if (from_parts)
-    hipLaunchKernelGGL(disaggregate_kernel<true>, grid, dim3(kBlock), 0, s, part,
-                       p.d_test_ptr, p.n_pairs(), (const float2*)E,
-                       p.d_nb_ptr, (const float2*)p.d_S, (const float2*)p.d_T, mode,
-                       (float2*)y, p.n_box, nb_total, p.nu, p.kh);
-  else
-    hipLaunchKernelGGL(disaggregate_kernel<false>, grid, dim3(kBlock), 0, s, part,
-                       p.d_test_ptr, p.n_pairs(), (const float2*)E,
-                       p.d_nb_ptr, (const float2*)p.d_S, (const float2*)p.d_T, mode,
-                       (float2*)y, p.n_box, nb_total, p.nu, p.kh);
+  const bool small = p.nu <= 84;  // at most 21 rows of E_j per lane
+#define UBF_DISAGG(PARTS, EQ)                                                     \
+  hipLaunchKernelGGL((disaggregate_kernel<PARTS, EQ>), grid, dim3(kBlock), 0, s, part, \
+                     p.d_test_ptr, p.n_pairs(), (const float2*)E, p.d_nb_ptr,     \
+                     (const float2*)p.d_S, (const float2*)p.d_T, mode, (float2*)y, \
+                     p.n_box, nb_total, p.nu, p.kh)
+  if (from_parts) {
+    if (small) UBF_DISAGG(true, 21); else UBF_DISAGG(true, 49);
+  } else {
+    if (small) UBF_DISAGG(false, 21); else UBF_DISAGG(false, 49);
+  }
+#undef UBF_DISAGG
   return (int)hipGetLastError();
 }
 

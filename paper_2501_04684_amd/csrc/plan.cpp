@@ -138,7 +138,8 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   L.test_ptr = take(p.test_ptr.size() * sizeof(int32_t));
   L.nb_ptr = take((size_t)(p.n_box + 1) * sizeof(int64_t));
   L.P = take((size_t)max_nrhs * p.n_box * p.pstride() * sizeof(float));
-  L.part = take((size_t)max_nrhs * p.n_pairs() * p.pstride() * sizeof(float));
+  // one spare row at the end receives the stores of idle matrix-core lanes
+  L.part = take(((size_t)max_nrhs * p.n_pairs() + 1) * p.pstride() * sizeof(float));
   L.total = at;
   return L;
 }
