@@ -27,6 +27,59 @@ if ROOT not in sys.path:
 
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E peak
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_04684_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_mvm_shell3338_hbm_traffic.json")
+STAGE_KERNELS = {"aggregate": "aggregate_kernel", "translate": "translate_mfma_kernel",
+                 "disaggregate": "disaggregate_kernel"}
+
+
+def source_hash(path=KERNEL_SOURCE):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_bytes):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the three stage kernels,
+    with the scale factors read off the plain device copy of copy_bytes."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        out = {}
+        for stage, name in STAGE_KERNELS.items():
+            vals = [float(r["Counter_Value"]) for r in rows if name in r["Kernel_Name"]]
+            out[stage] = statistics.median(vals) if vals else None
+        copies = [float(r["Counter_Value"]) for r in rows
+                  if "copyBuffer" in r["Kernel_Name"]]
+        return out, max(copies)
+
+    fetch, fetch_copy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, write_copy = per_kernel(write_csv, "WRITE_SIZE")
+    return {
+        "source_sha256": source_hash(),
+        "copy_bytes": copy_bytes,
+        "copy_fetch_kib": fetch_copy, "copy_write_kib": write_copy,
+        "fetch_scale": copy_bytes / 1024.0 / fetch_copy,
+        "write_scale": copy_bytes / 1024.0 / write_copy,
+        "fetch_kib": fetch, "write_kib": write,
+    }
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of `stage` from the committed counter summary,
+    or None when it is missing or the kernel source changed since."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash():
+        return None
+    f, w = t["fetch_kib"].get(stage), t["write_kib"].get(stage)
+    if f is None or w is None:
+        return None
+    return 1024.0 * (f * t["fetch_scale"] + w * t["write_scale"])
 
 
 def parse():
@@ -41,6 +94,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the counter summary of two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) made with --copy-mb, and exit")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing "
                          "(reference kernel for scaling hardware byte counters)")
@@ -87,6 +143,10 @@ def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc,
+                                       (args.copy_mb or 256) << 20), indent=1))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
@@ -160,13 +220,14 @@ def main():
         ach = flops / (avg_us[1] * 1e-6) / 1e12
         roof = {"kernel": "translate", "bound": "mfma", "achieved": ach,
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
+                "frac": ach / PEAK_FP32_MFMA_TFLOPS,
+                "traffic": measured_traffic("translate")}
     else:
         b = bytes_agg if dom == 0 else bytes_dis
         ach = b / (avg_us[dom] * 1e-6) / 1e9
         roof = {"kernel": stage_names[dom], "bound": "hbm", "achieved": ach,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                "traffic": None}
+                "traffic": measured_traffic(stage_names[dom])}
     trans_tflops = flops / (avg_us[1] * 1e-6) / 1e12
     stages = {
         name: {"avg_us": float(avg_us[i])} for i, name in enumerate(stage_names)}
@@ -175,6 +236,11 @@ def main():
     if S is not None:
         stages["aggregate"]["gbs"] = bytes_agg / (avg_us[0] * 1e-6) / 1e9
         stages["disaggregate"]["gbs"] = bytes_dis / (avg_us[2] * 1e-6) / 1e9
+    stages["aggregate"]["algorithmic_bytes"] = bytes_agg
+    stages["disaggregate"]["algorithmic_bytes"] = bytes_dis
+    stages["translate"]["algorithmic_flops"] = flops
+    for name in stage_names:
+        stages[name]["traffic"] = measured_traffic(name)
 
     out = {
         "metric": "far-zone MVMs/s", "value": value, "unit": "MVM/s",
