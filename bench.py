@@ -9,9 +9,15 @@ basis functions per box), as an iterative solver would issue it. Inputs
 (50 seeded vectors, cycled) and the basis matrices are resident in HBM
 before timing starts; the plan (far set, operator table) is built once.
 
+The headline form is the split-precision translation (BF16 hi/lo operands,
+three products, FP32 accumulation), which stays within the 1e-4 relative
+error of the plain FP32 form; the plain FP32 form is timed after it and
+reported under "compare" with the speedup.
+
 Prints one JSON line with the throughput, latency percentiles, the
 roofline position of the dominant kernel (timed with HIP events on the
-stream it runs on) and the FP64 CPU oracle timed on a bounded sample.
+stream it runs on) and the FP64 CPU oracle timed on a bounded sample,
+with the relative l2 error of both forms against it.
 """
 from __future__ import annotations
 
@@ -27,9 +33,12 @@ if ROOT not in sys.path:
 
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_04684_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_mvm_shell3338_hbm_traffic.json")
-STAGE_KERNELS = {"aggregate": "aggregate_kernel", "translate": "translate_mfma_kernel",
+STAGE_KERNELS = {"aggregate": "aggregate_kernel",
+                 "translate_mfma": "translate_mfma_kernel",
+                 "translate_split": "translate_split_kernel",
                  "disaggregate": "disaggregate_kernel"}
 
 
@@ -94,6 +103,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["split-bf16", "fp32"], default="split-bf16",
+                    help="form timed for the headline value (the other form is "
+                         "timed after it for comparison unless --no-compare)")
+    ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the counter summary of two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) made with --copy-mb, and exit")
@@ -141,6 +154,60 @@ def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
     }, rel
 
 
+def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0):
+    """Build the plan for one precision form, time `steps` MVMs after
+    `warmup` untimed ones, and return the measurements."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=nrhs,
+                    precision=precision)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    nb_ptr = S = S_dev = None
+    if basis == "synthetic":
+        nb = np.full(w.n_box, w.n_u)
+        nb_ptr, S = W.random_basis(nb, w.n_u, seed=w.seed)
+        S_dev = torch.from_numpy(S).to(dev)
+        ff.set_basis(nb_ptr, S_dev)
+    nb_total = ff.nb_total
+    n_vec = 50
+    X = torch.from_numpy(W.complex_normal((n_vec, nrhs, nb_total), seed=1000)).to(dev)
+    Y = torch.empty((nrhs, nb_total), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    if copy_mb > 0:  # reference kernel for scaling hardware byte counters
+        src = torch.ones(copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for s in range(warmup):
+        U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
+    torch.cuda.synchronize()
+
+    U.profile_begin(ff.plan, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stage_ms, call_ms = U.profile_end(ff.plan, steps)
+
+    U.far_mvm(ff.plan, X[0], Y, nrhs, stream)  # first vector, for accuracy
+    torch.cuda.synchronize()
+    out = {"info": ff.info, "plan_ms": plan_ms, "dt": dt, "value": steps * nrhs / dt,
+           "avg_us": stage_ms / steps * 1e3, "call_ms": call_ms,
+           "y0": Y.cpu().numpy(), "x0": X[0].cpu().numpy(), "nb_ptr": nb_ptr, "S": S,
+           "nb_total": nb_total}
+    ff.close()
+    del S_dev
+    return out
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -157,113 +224,100 @@ def main():
     import paper_2501_04684_amd as U
     import workloads as W
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     w = W.config(args.workload)
     nrhs = args.nrhs
+    chosen = args.precision
+    res = run_form(U, W, torch, w, chosen, args.basis, nrhs, args.warmup, args.steps,
+                   args.copy_mb)
+    other = None
+    if not args.no_compare:
+        other_form = "fp32" if chosen != "fp32" else "split-bf16"
+        other = run_form(U, W, torch, w, other_form, args.basis, nrhs, args.warmup,
+                         args.steps)
 
-    t0 = time.perf_counter()
-    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=nrhs)
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    info = ff.info
-
-    nb_ptr = S = None
-    if args.basis == "synthetic":
-        nb = np.full(w.n_box, w.n_u)
-        nb_ptr, S = W.random_basis(nb, w.n_u, seed=w.seed)
-        S_dev = torch.from_numpy(S).to(dev)
-        ff.set_basis(nb_ptr, S_dev)
-    nb_total = ff.nb_total
-    n_vec = 50
-    X = torch.from_numpy(W.complex_normal((n_vec, nrhs, nb_total), seed=1000)).to(dev)
-    Y = torch.empty((nrhs, nb_total), dtype=torch.complex64, device=dev)
-    stream = torch.cuda.current_stream().cuda_stream
-
-    if args.copy_mb > 0:
-        src = torch.ones(args.copy_mb << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    for s in range(args.warmup):
-        U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
-    torch.cuda.synchronize()
-
-    K = args.steps
-    U.profile_begin(ff.plan, K)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(K):
-        U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stage_ms, call_ms = U.profile_end(ff.plan, K)
-
-    # result of the first vector, for the accuracy figure
-    U.far_mvm(ff.plan, X[0], Y, nrhs, stream)
-    torch.cuda.synchronize()
-    y0 = Y.cpu().numpy()
-
-    value = K * nrhs / dt
-    avg_us = stage_ms / K * 1e3
+    info, avg_us, S = res["info"], res["avg_us"], res["S"]
+    nb_total, K, dt = res["nb_total"], args.steps, res["dt"]
     n_pairs, n_box, nu = info["n_pairs"], info["n_boxes"], info["n_u"]
     s_bytes = 0 if S is None else S.nbytes
     stage_names = ["aggregate", "translate", "disaggregate"]
+    split = chosen == "split-bf16"
+    translate_kernel = "translate_split" if split else "translate_mfma"
     # algorithmic work per launch
     flops = info["translate_flops"] * nrhs
     bytes_agg = s_bytes + nrhs * (nb_total + n_box * nu) * 8
     bytes_dis = s_bytes + nrhs * (n_box * nu + nb_total) * 8
+    trans_tflops = flops / (avg_us[1] * 1e-6) / 1e12
+    # split form: three BF16 products over 32-row blocks and 8-wide k-steps
+    khb = (nu + 7) // 8 * 8
+    issued = 3 * 2 * (-(-2 * nu // 32) * 32) * (2 * khb) * n_pairs * nrhs
     dom = int(np.argmax(avg_us))
     if dom == 1:
-        ach = flops / (avg_us[1] * 1e-6) / 1e12
-        roof = {"kernel": "translate", "bound": "mfma", "achieved": ach,
-                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP32_MFMA_TFLOPS,
-                "traffic": measured_traffic("translate")}
+        peak = PEAK_BF16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
+        ach = (issued if split else flops) / (avg_us[1] * 1e-6) / 1e12
+        roof = {"kernel": translate_kernel, "bound": "mfma", "achieved": ach,
+                "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": measured_traffic(translate_kernel)}
     else:
         b = bytes_agg if dom == 0 else bytes_dis
         ach = b / (avg_us[dom] * 1e-6) / 1e9
         roof = {"kernel": stage_names[dom], "bound": "hbm", "achieved": ach,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                 "traffic": measured_traffic(stage_names[dom])}
-    trans_tflops = flops / (avg_us[1] * 1e-6) / 1e12
-    stages = {
-        name: {"avg_us": float(avg_us[i])} for i, name in enumerate(stage_names)}
-    stages["translate"].update(tflops=trans_tflops,
-                               frac_fp32_mfma=trans_tflops / PEAK_FP32_MFMA_TFLOPS)
-    if S is not None:
-        stages["aggregate"]["gbs"] = bytes_agg / (avg_us[0] * 1e-6) / 1e9
-        stages["disaggregate"]["gbs"] = bytes_dis / (avg_us[2] * 1e-6) / 1e9
-    stages["aggregate"]["algorithmic_bytes"] = bytes_agg
-    stages["disaggregate"]["algorithmic_bytes"] = bytes_dis
-    stages["translate"]["algorithmic_flops"] = flops
-    for name in stage_names:
-        stages[name]["traffic"] = measured_traffic(name)
+    stages = {name: {"avg_us": float(avg_us[i])} for i, name in enumerate(stage_names)}
+    stages["translate"].update(
+        kernel=translate_kernel, algorithmic_flops=flops,
+        tflops=trans_tflops, frac_fp32_mfma_peak=trans_tflops / PEAK_FP32_MFMA_TFLOPS,
+        traffic=measured_traffic(translate_kernel))
+    if split:
+        itf = issued / (avg_us[1] * 1e-6) / 1e12
+        stages["translate"].update(issued_bf16_flops=issued, issued_tflops=itf,
+                                   frac_bf16_mfma_peak=itf / PEAK_BF16_MFMA_TFLOPS)
+    for i, (name, b) in enumerate((("aggregate", bytes_agg), ("disaggregate", bytes_dis))):
+        st = stages[name]
+        st["algorithmic_bytes"] = b
+        st["gbs"] = b / (st["avg_us"] * 1e-6) / 1e9
+        st["traffic"] = measured_traffic(name)
 
     out = {
-        "metric": "far-zone MVMs/s", "value": value, "unit": "MVM/s",
+        "metric": "far-zone MVMs/s", "value": res["value"], "unit": "MVM/s",
         "n_gpus": 1, "steps": K, "warmup": args.warmup,
         "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None,
+        "dtype": "f32 (stage 2 bf16 hi/lo x3, f32 accumulation)" if split else "f32",
+        "data": "synthetic",
         "config": {"workload": w.name, "n_boxes": n_box, "n_pairs": n_pairs,
                    "n_offsets": info["n_offsets"], "n_u": nu, "far_mode": w.far_mode,
                    "basis": (f"synthetic, {w.n_u} functions per box"
                              if S is not None else "identity"),
-                   "nrhs": nrhs},
-        "p50_ms": float(np.percentile(call_ms, 50)),
-        "p99_ms": float(np.percentile(call_ms, 99)),
-        "plan_ms": plan_ms,
+                   "nrhs": nrhs, "precision": chosen},
+        "p50_ms": float(np.percentile(res["call_ms"], 50)),
+        "p99_ms": float(np.percentile(res["call_ms"], 99)),
+        "plan_ms": res["plan_ms"],
         "stages": stages,
         "roofline": roof,
     }
+    if other is not None:
+        ot = other["avg_us"]
+        out["compare"] = {
+            "precision": "fp32" if chosen != "fp32" else "split-bf16",
+            "value": other["value"], "translate_us": float(ot[1]),
+            "p50_ms": float(np.percentile(other["call_ms"], 50)),
+            "speedup_of_chosen": res["value"] / other["value"],
+            "translate_speedup_of_chosen": float(ot[1] / avg_us[1]),
+        }
     if not args.no_cpu_baseline:
-        cb, rel = cpu_baseline(w, nb_ptr, S, X[0].cpu().numpy(), y0, args.cpu_seconds)
+        cb, rel = cpu_baseline(w, res["nb_ptr"], S, res["x0"], res["y0"], args.cpu_seconds)
         out["cpu_baseline"] = cb
         out["rel_l2_vs_oracle"] = rel
+        if other is not None:
+            import oracle as O
+            yref = O.far_mvm(other["x0"].astype(np.complex128), w.boxes, w.a, w.k, w.n_d,
+                             other["nb_ptr"], None if other["S"] is None
+                             else other["S"].astype(np.complex128), mode=w.far_mode)
+            out["compare"]["rel_l2_vs_oracle"] = float(
+                np.linalg.norm(other["y0"] - yref) / np.linalg.norm(yref))
     print(json.dumps(out))
-    ff.close()
     return 0
 
 

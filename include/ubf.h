@@ -71,7 +71,12 @@ enum ubf_far_mode {
 };
 
 enum ubf_precision {
-  UBF_FP32 = 0       /* FP32 operands, FP32 accumulation */
+  UBF_FP32 = 0,       /* FP32 operands, FP32 accumulation */
+  UBF_SPLIT_BF16 = 1  /* stage 2 with operators and coefficients each split
+                         into a BF16 high part and a BF16 remainder,
+                         G P ~ Gh Ph + Gh Pl + Gl Ph on the BF16 matrix cores
+                         with FP32 accumulation (stages 1 and 3 stay FP32);
+                         n_d 1..3 */
 };
 
 /* Problem statement (Sec. 2: box grid, dipoles per box, wavenumber). */
@@ -99,7 +104,7 @@ typedef struct ubf_info {
   int64_t table_bytes;      /* device operator table */
   double translate_flops;   /* real flops per RHS: 8 * n_u^2 * n_pairs */
   int32_t mfma;             /* 1 if stage 2 runs on the matrix cores */
-  int32_t reserved;
+  int32_t precision;        /* enum ubf_precision of the plan */
 } ubf_info;
 
 typedef struct ubf_plan ubf_plan;
@@ -109,8 +114,9 @@ typedef struct ubf_plan ubf_plan;
  * orbits (Sec. 2.2), the work partition, and the FP32 operator table
  * from FP64 evaluations of Eq. (5)-(6) and (13).
  * Errors: UBF_EINVAL for a null pointer, n_boxes < 1, a negative or
- * duplicate coordinate, a <= 0, k <= 0, eta < 0, n_d outside 1..4, an
- * unknown far_mode or precision, or a far set beyond 2^31-1 pairs;
+ * duplicate coordinate, a <= 0, k <= 0, eta < 0, n_d outside 1..4 (1..3
+ * for UBF_SPLIT_BF16), an unknown far_mode or precision, or a far set
+ * beyond 2^31-1 pairs;
  * UBF_ENOMEM if host memory runs out. *out is set only on success. */
 int ubf_plan_create(const ubf_problem* problem, ubf_plan** out);
 

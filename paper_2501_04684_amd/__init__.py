@@ -18,7 +18,7 @@ import re
 import numpy as np
 
 __all__ = [
-    "UbfError", "FAR_ILIST", "FAR_FULL", "FP32", "lib", "library_path",
+    "UbfError", "FAR_ILIST", "FAR_FULL", "FP32", "SPLIT_BF16", "lib", "library_path",
     "declared_symbols", "plan_create", "workspace_bytes", "plan_bind",
     "plan_set_basis", "far_mvm", "aggregate", "translate", "disaggregate",
     "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
@@ -32,7 +32,9 @@ HEADER = os.path.join(ROOT, "include", "ubf.h")
 library_path = os.path.join(HERE, "libubf.so")
 
 FAR_ILIST, FAR_FULL = 0, 1
-FP32 = 0
+FP32, SPLIT_BF16 = 0, 1
+_PRECISIONS = {"fp32": FP32, "split-bf16": SPLIT_BF16, FP32: FP32,
+               SPLIT_BF16: SPLIT_BF16}
 _MODES = {"ilist": FAR_ILIST, "full": FAR_FULL, FAR_ILIST: FAR_ILIST,
           FAR_FULL: FAR_FULL}
 
@@ -58,7 +60,7 @@ class _Info(ctypes.Structure):
                 ("n_u", ctypes.c_int32), ("n_d", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("translate_flops", ctypes.c_double), ("mfma", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32)]
 
 
 _lib = None
@@ -145,7 +147,7 @@ def plan_create(boxes, a: float, k: float, n_d: int, far_mode="ilist",
     """Create a plan from integer box coordinates (n, 3). Host only."""
     b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 3))
     prob = _Problem(len(b), b.ctypes.data, float(a), float(k), float(eta),
-                    int(n_d), _MODES[far_mode], int(precision))
+                    int(n_d), _MODES[far_mode], _PRECISIONS[precision])
     out = _VP()
     _check(lib().ubf_plan_create(ctypes.byref(prob), ctypes.byref(out)),
            "ubf_plan_create")
@@ -202,8 +204,7 @@ def disaggregate(plan, E, y, nrhs=None, stream=None):
 def plan_info(plan) -> dict:
     info = _Info()
     _check(lib().ubf_plan_info(plan, ctypes.byref(info)), "ubf_plan_info")
-    return {name: getattr(info, name) for name, _ in _Info._fields_
-            if name != "reserved"}
+    return {name: getattr(info, name) for name, _ in _Info._fields_}
 
 
 def plan_offsets(plan) -> np.ndarray:
@@ -260,9 +261,9 @@ class FarField:
     """
 
     def __init__(self, boxes, a, k, n_d, far_mode="ilist", eta=0.0,
-                 max_nrhs=1, device="cuda"):
+                 max_nrhs=1, device="cuda", precision=FP32):
         import torch
-        self.plan = plan_create(boxes, a, k, n_d, far_mode, eta)
+        self.plan = plan_create(boxes, a, k, n_d, far_mode, eta, precision)
         self.info = plan_info(self.plan)
         self.max_nrhs = int(max_nrhs)
         nbytes = workspace_bytes(self.plan, self.max_nrhs)

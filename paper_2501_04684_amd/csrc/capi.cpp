@@ -128,7 +128,8 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
     for (int64_t i = 0; i <= p.n_box; ++i) nb[i] = i * p.nu;
   }
   const Copy copies[] = {
-      {L.table, p.table.data(), p.table.size() * sizeof(float)},
+      {L.table, p.split() ? (const void*)p.table_bf16.data() : (const void*)p.table.data(),
+       p.table_bytes()},
       {L.chunks, p.chunks.data(), p.chunks.size() * sizeof(int32_t)},
       {L.wg_ptr, p.wg_ptr.data(), p.wg_ptr.size() * sizeof(int32_t)},
       {L.pair_src, p.pair_src.data(), p.pair_src.size() * sizeof(int32_t)},
@@ -317,9 +318,10 @@ int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
   out->n_u = p.nu;
   out->n_d = p.n_d;
   out->n_chunks = p.n_chunks();
-  out->table_bytes = (int64_t)(p.table.size() * sizeof(float));
+  out->table_bytes = (int64_t)p.table_bytes();
   out->translate_flops = 8.0 * p.nu * (double)p.nu * (double)p.n_pairs();
   out->mfma = ubf::translate_uses_mfma(p) ? 1 : 0;
+  out->precision = p.precision;
   return ok();
 }
 

@@ -14,6 +14,35 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even FP32 -> BF16 bits (finite inputs), and back.
+__device__ inline unsigned bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ inline float bf16_f(unsigned b) { return __uint_as_float(b << 16); }
+
+// Writes one box-vector coefficient (re, im) at index u of a box vector
+// starting at Pb: FP32 layout [re(kh) | im(kh)] or split layout
+// [re.hi | re.lo | im.hi | im.lo] of khb BF16 values each (hi = bf16(v),
+// lo = bf16(v - hi)).
+__device__ inline void put_coef(float* Pb, int u, float re, float im, int kh, int khb,
+                                bool split) {
+  if (!split) {
+    Pb[u] = re;
+    Pb[kh + u] = im;
+    return;
+  }
+  unsigned short* q = reinterpret_cast<unsigned short*>(Pb);
+  const unsigned rh = bf16_rne(re), ih = bf16_rne(im);
+  q[u] = (unsigned short)rh;
+  q[khb + u] = (unsigned short)bf16_rne(re - bf16_f(rh));
+  q[2 * khb + u] = (unsigned short)ih;
+  q[3 * khb + u] = (unsigned short)bf16_rne(im - bf16_f(ih));
+}
 
 constexpr int kBlock = 256;
 
@@ -36,27 +65,36 @@ __device__ inline int xcd_chunk(int bid, int grid) {
 
 __global__ __launch_bounds__(kBlock) void pack_kernel(
     const float2* __restrict__ x, float* __restrict__ P, int64_t n_rows,
-    int nu, int kh) {
-  const int64_t total = n_rows * kh;
+    int nu, int kh, int khb, int split) {
+  const int len = split ? khb : kh;            // coefficients incl. zero pad
+  const int vs = split ? 2 * khb : 2 * kh;     // box vector stride (floats)
+  const int64_t total = n_rows * len;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int u = (int)(t % kh);
-    const int64_t row = t / kh;
+    const int u = (int)(t % len);
+    const int64_t row = t / len;
     const float2 v = u < nu ? x[row * nu + u] : make_float2(0.f, 0.f);
-    P[row * 2 * kh + u] = v.x;
-    P[row * 2 * kh + kh + u] = v.y;
+    put_coef(P + row * vs, u, v.x, v.y, kh, khb, split != 0);
   }
 }
 
 __global__ __launch_bounds__(kBlock) void unpack_kernel(
     const float* __restrict__ P, float2* __restrict__ out, int64_t n_rows,
-    int nu, int kh) {
+    int nu, int kh, int khb, int split) {
+  const int vs = split ? 2 * khb : 2 * kh;
   const int64_t total = n_rows * nu;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int u = (int)(t % nu);
     const int64_t row = t / nu;
-    out[t] = make_float2(P[row * 2 * kh + u], P[row * 2 * kh + kh + u]);
+    const float* Pb = P + row * vs;
+    if (!split) {
+      out[t] = make_float2(Pb[u], Pb[kh + u]);
+    } else {
+      const unsigned short* q = reinterpret_cast<const unsigned short*>(Pb);
+      out[t] = make_float2(bf16_f(q[u]) + bf16_f(q[khb + u]),
+                           bf16_f(q[2 * khb + u]) + bf16_f(q[3 * khb + u]));
+    }
   }
 }
 
@@ -69,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(
 __global__ __launch_bounds__(kBlock) void aggregate_kernel(
     const float2* __restrict__ x, const int64_t* __restrict__ nb_ptr,
     const float2* __restrict__ S, float* __restrict__ P, int64_t n_box,
-    int64_t nb_total, int nu, int kh) {
+    int64_t nb_total, int nu, int kh, int khb, int split) {
   __shared__ float2 red[kBlock];
   const int64_t i = blockIdx.x;
   const int r = blockIdx.y;
@@ -94,16 +132,16 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(
   }
   red[t] = make_float2(ar, ai);
   __syncthreads();
-  float* Pb = P + ((int64_t)r * n_box + i) * 2 * kh;
-  for (int v = t; v < kh; v += kBlock) {
+  float* Pb = P + ((int64_t)r * n_box + i) * (split ? 2 * khb : 2 * kh);
+  const int len = split ? khb : kh;
+  for (int v = t; v < len; v += kBlock) {
     float sr = 0.f, si = 0.f;
     if (v < nu)
       for (int gg = 0; gg < G; ++gg) {
         sr += red[gg * nu + v].x;
         si += red[gg * nu + v].y;
       }
-    Pb[v] = sr;
-    Pb[kh + v] = si;
+    put_coef(Pb, v, sr, si, kh, khb, split != 0);
   }
 }
 
@@ -321,6 +359,166 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
       }
 #pragma unroll
       for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb1[ks];
+      src2 = pair_src[i2];
+      dst2 = pair_dst[i2];
+    }
+    o0 = o1; n0 = n1; dst0 = dst1;
+    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;
+  }
+}
+
+// Split-precision translation on the BF16 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation). With G = Gh + Gl and
+// P = Ph + Pl (h = bf16 of the value, l = bf16 of the remainder), the
+// product is taken as Gh Ph + Gh Pl + Gl Ph; the dropped Gl Pl term and the
+// representation error of each split are about 2^-16 relative. Work
+// layout, pipelining and stores are those of translate_mfma_kernel: lane l
+// owns column l % 32 and K half h = l / 32; a k-step covers 8 consecutive
+// values of each half (KHB = NU rounded up to 8, zero padded), read as one
+// 16-byte value per lane; the operator's four BF16 planes (re.hi, re.lo,
+// im.hi, im.lo) sit in LDS and -Gi is a sign flip. 32-row blocks cover
+// all 2*NU rows (padding rows read row 0 and are not stored).
+template <int NU>
+__global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
+    const unsigned short* __restrict__ table, const int32_t* __restrict__ chunks,
+    const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
+    const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
+    float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row) {
+  constexpr int KH = (NU + 3) & ~3;      // FP32 half-length (partial rows)
+  constexpr int KHB = (NU + 7) & ~7;     // BF16 half-length
+  constexpr int PLANE = NU * KHB;        // BF16 values per plane
+  constexpr int M = 2 * NU;
+  constexpr int RB = (M + 31) / 32;
+  constexpr int NGB = KHB / 8;           // k-steps per half
+  constexpr int PSTR = 2 * KH;           // partial row (floats)
+  constexpr int VSTR = 2 * KHB;          // box vector (floats)
+  constexpr int N4 = 4 * PLANE * 2 / 16; // 16-byte units per operator
+  constexpr int LD = (N4 + kBlock - 1) / kBlock;
+  __shared__ uintx4 lds4[N4];
+  const unsigned short* lds = reinterpret_cast<const unsigned short*>(lds4);
+
+  const int group = xcd_chunk(blockIdx.x, gridDim.x);
+  const int cbeg = wg_ptr[group], cend = wg_ptr[group + 1];
+  const int rhs = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+
+  // Operator rows of this lane per block: Er rows read re (h = 0) or -im
+  // (h = 1); Ei rows read im (h = 0) or re (h = 1). hi plane = 2c, lo = 2c+1.
+  int abase[RB];
+  unsigned asgn[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int row = rb * 32 + r;
+    const bool er = row < NU;
+    const int rr = er ? row : (row < M ? row - NU : 0);
+    const int c = er ? (h == 1 ? 1 : 0) : (row < M && h == 0 ? 1 : 0);
+    abase[rb] = 2 * c * PLANE + rr * KHB;
+    asgn[rb] = (er && h == 1) ? 0x80008000u : 0u;
+  }
+
+  if (cbeg >= cend) return;
+  const int col0 = wave * 32;
+  const int64_t last = n_pairs - 1;
+
+  // As in translate_mfma_kernel: unconditional memory operations, pair
+  // indices two chunks ahead, B values one chunk ahead (ring refill).
+  int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
+  const bool has1 = cbeg + 1 < cend;
+  int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
+  int b1 = has1 ? chunks[4 * (cbeg + 1) + 1] : 0;
+  int n1 = has1 ? chunks[4 * (cbeg + 1) + 2] : 0;
+  int64_t i0 = min((int64_t)b0 + col0 + r, last), i1 = min((int64_t)b1 + col0 + r, last);
+  int src0 = pair_src[i0], dst0 = pair_dst[i0];
+  int src1 = pair_src[i1], dst1 = pair_dst[i1];
+
+  bf16x8 bh[NGB], bl[NGB];
+  {
+    const bf16x8* pv = reinterpret_cast<const bf16x8*>(
+        P + ((int64_t)rhs * n_box + src0) * VSTR + h * KHB);
+#pragma unroll
+    for (int g = 0; g < NGB; ++g) {
+      bh[g] = pv[g];
+      bl[g] = pv[NGB + g];
+    }
+  }
+
+  int staged = -1;
+  for (int ch = cbeg; ch < cend; ++ch) {
+    if (o0 != staged) {  // uniform across the workgroup
+      __syncthreads();
+      const uintx4* g4 = reinterpret_cast<const uintx4*>(table + (size_t)o0 * 4 * PLANE);
+      uintx4 tmp[LD];
+#pragma unroll
+      for (int it = 0; it < LD; ++it) tmp[it] = g4[min((int)threadIdx.x + it * kBlock, N4 - 1)];
+#pragma unroll
+      for (int it = 0; it < LD; ++it) {
+        const int i = threadIdx.x + it * kBlock;
+        if (i < N4) lds4[i] = tmp[it];
+      }
+      __syncthreads();
+      staged = o0;
+    }
+    const bool has2 = ch + 2 < cend;
+    const int o2 = has2 ? chunks[4 * (ch + 2)] : o1;
+    const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
+    const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
+    const int64_t i2 = min((int64_t)b2 + col0 + r, last);
+    const bf16x8* pv1 = reinterpret_cast<const bf16x8*>(
+        P + ((int64_t)rhs * n_box + src1) * VSTR + h * KHB);
+    int src2, dst2;
+
+    if (col0 < n0) {  // wave-uniform
+      floatx16 acc[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+#pragma unroll
+      for (int g = 0; g < NGB; ++g) {
+        bf16x8 a_h[RB], a_l[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          uintx4 ah = *reinterpret_cast<const uintx4*>(lds + abase[rb] + 8 * g);
+          uintx4 al = *reinterpret_cast<const uintx4*>(lds + abase[rb] + PLANE + 8 * g);
+          ah ^= asgn[rb];
+          al ^= asgn[rb];
+          a_h[rb] = __builtin_bit_cast(bf16x8, ah);
+          a_l[rb] = __builtin_bit_cast(bf16x8, al);
+        }
+        // consecutive MFMAs go to different row blocks (independent
+        // accumulators); each block's three products are RB issues apart
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h[rb], bh[g], acc[rb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h[rb], bl[g], acc[rb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l[rb], bh[g], acc[rb], 0, 0, 0);
+        bh[g] = pv1[g];  // next chunk
+        bl[g] = pv1[NGB + g];
+      }
+      src2 = pair_src[i2];
+      dst2 = pair_dst[i2];
+
+      const int64_t row = (col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
+      float* out = part + row * PSTR;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int r0 = rb * 32 + 8 * q4 + 4 * h;
+          if (rb * 32 + 8 * q4 + 8 <= PSTR)  // same for both halves h
+            *reinterpret_cast<floatx4*>(out + r0) =
+                floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                        acc[rb][4 * q4 + 3]};
+        }
+    } else {  // no column of this chunk for this wavefront: fetch the next
+#pragma unroll
+      for (int g = 0; g < NGB; ++g) {
+        bh[g] = pv1[g];
+        bl[g] = pv1[NGB + g];
+      }
       src2 = pair_src[i2];
       dst2 = pair_dst[i2];
     }
@@ -620,15 +818,17 @@ bool translate_uses_mfma(const Plan& p) {
 
 int launch_pack(const Plan& p, const void* x, float* P, int nrhs, void* stream) {
   const int64_t rows = (int64_t)nrhs * p.n_box;
-  hipLaunchKernelGGL(pack_kernel, dim3(grid_for(rows * p.kh)), dim3(kBlock), 0,
-                     (hipStream_t)stream, (const float2*)x, P, rows, p.nu, p.kh);
+  hipLaunchKernelGGL(pack_kernel, dim3(grid_for(rows * (p.split() ? p.khb : p.kh))),
+                     dim3(kBlock), 0, (hipStream_t)stream, (const float2*)x, P, rows,
+                     p.nu, p.kh, p.khb, p.split() ? 1 : 0);
   return (int)hipGetLastError();
 }
 
 int launch_unpack(const Plan& p, const float* P, void* out, int nrhs, void* stream) {
   const int64_t rows = (int64_t)nrhs * p.n_box;
   hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(rows * p.nu)), dim3(kBlock), 0,
-                     (hipStream_t)stream, P, (float2*)out, rows, p.nu, p.kh);
+                     (hipStream_t)stream, P, (float2*)out, rows, p.nu, p.kh, p.khb,
+                     p.split() ? 1 : 0);
   return (int)hipGetLastError();
 }
 
@@ -636,7 +836,8 @@ int launch_aggregate(const Plan& p, const void* x, float* P, int nrhs, void* str
   if (!p.has_basis) return launch_pack(p, x, P, nrhs, stream);
   hipLaunchKernelGGL(aggregate_kernel, dim3((unsigned)p.n_box, nrhs), dim3(kBlock), 0,
                      (hipStream_t)stream, (const float2*)x, p.d_nb_ptr,
-                     (const float2*)p.d_S, P, p.n_box, p.nb_total(), p.nu, p.kh);
+                     (const float2*)p.d_S, P, p.n_box, p.nb_total(), p.nu, p.kh,
+                     p.khb, p.split() ? 1 : 0);
   return (int)hipGetLastError();
 }
 
@@ -646,21 +847,37 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
   if (nch == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
   const dim3 groups((unsigned)p.n_groups(), nrhs);
+  const int64_t trash = (int64_t)p.max_nrhs * p.n_pairs();
+  if (p.split()) {
+    const unsigned short* tb = reinterpret_cast<const unsigned short*>(p.d_table);
+#define UBF_SPLIT(NU)                                                                  \
+  hipLaunchKernelGGL(translate_split_kernel<NU>, groups, dim3(kBlock), 0, s, tb,         \
+                     p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,        \
+                     p.n_box, p.n_pairs(), trash)
+    switch (p.nu) {
+      case 81: UBF_SPLIT(81); break;
+      case 24: UBF_SPLIT(24); break;
+      case 3: UBF_SPLIT(3); break;
+      default: return (int)hipErrorInvalidValue;  // rejected at plan creation
+    }
+#undef UBF_SPLIT
+    return (int)hipGetLastError();
+  }
   switch (p.nu) {
     case 81:
       hipLaunchKernelGGL(translate_mfma_kernel<81>, groups, dim3(kBlock), 0, s,
                          p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs(), (int64_t)p.max_nrhs * p.n_pairs());
+                         p.n_box, p.n_pairs(), trash);
       break;
     case 24:
       hipLaunchKernelGGL(translate_mfma_kernel<24>, groups, dim3(kBlock), 0, s,
                          p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs(), (int64_t)p.max_nrhs * p.n_pairs());
+                         p.n_box, p.n_pairs(), trash);
       break;
     case 3:
       hipLaunchKernelGGL(translate_mfma_kernel<3>, groups, dim3(kBlock), 0, s,
                          p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs(), (int64_t)p.max_nrhs * p.n_pairs());
+                         p.n_box, p.n_pairs(), trash);
       break;
     default:
       hipLaunchKernelGGL(translate_generic_kernel, dim3((unsigned)nch, nrhs),

@@ -130,14 +130,14 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
     at = align256(at + bytes);
     return here;
   };
-  L.table = take(p.table.size() * sizeof(float));
+  L.table = take(p.table_bytes());
   L.chunks = take(p.chunks.size() * sizeof(int32_t));
   L.wg_ptr = take(p.wg_ptr.size() * sizeof(int32_t));
   L.pair_src = take(p.pair_src.size() * sizeof(int32_t));
   L.pair_dst = take(p.pair_dst.size() * sizeof(int32_t));
   L.test_ptr = take(p.test_ptr.size() * sizeof(int32_t));
   L.nb_ptr = take((size_t)(p.n_box + 1) * sizeof(int64_t));
-  L.P = take((size_t)max_nrhs * p.n_box * p.pstride() * sizeof(float));
+  L.P = take((size_t)max_nrhs * p.n_box * p.vstride() * sizeof(float));
   // one spare row at the end receives the stores of idle matrix-core lanes
   L.part = take(((size_t)max_nrhs * p.n_pairs() + 1) * p.pstride() * sizeof(float));
   L.total = at;
@@ -155,7 +155,8 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   if (!(eta >= 0.0) || !std::isfinite(eta)) return "eta must be >= 0 (0 = free space)";
   if (n_d < 1 || n_d > 4) return "n_d must be in 1..4";
   if (far_mode != 0 && far_mode != 1) return "unknown far_mode";
-  if (precision != 0) return "unknown precision";
+  if (precision != 0 && precision != 1) return "unknown precision";
+  if (precision == 1 && n_d > 3) return "split precision supports n_d 1..3";
 
   P.n_box = n_box;
   P.boxes.assign(box_ijk, box_ijk + 3 * n_box);
@@ -167,6 +168,7 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   P.n_d = n_d;
   P.nu = 3 * n_d * n_d * n_d;
   P.kh = half_len(P.nu);
+  P.khb = half_len_bf16(P.nu);
   P.far_mode = far_mode;
   P.precision = precision;
 
@@ -216,7 +218,9 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   std::sort(uniq.begin(), uniq.end());
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
   const int64_t n_off = (int64_t)uniq.size();
-  const double table_bytes = (double)n_off * 2.0 * P.nu * P.kh * sizeof(float);
+  const double table_bytes = precision == 1
+      ? (double)n_off * 4.0 * P.nu * half_len_bf16(P.nu) * sizeof(uint16_t)
+      : (double)n_off * 2.0 * P.nu * P.kh * sizeof(float);
   if (table_bytes > kMaxTableBytes) return "operator table would exceed 16 GiB";
   P.offsets.resize(3 * n_off);
   for (int64_t o = 0; o < n_off; ++o)
@@ -297,18 +301,40 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   P.n_orbits = (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
 
   // Operator table image.
-  const size_t plane = P.plane_floats();
-  P.table.assign((size_t)n_off * 2 * plane, 0.0f);
   std::vector<std::complex<double>> G;
-  for (int64_t o = 0; o < n_off; ++o) {
-    operator_fp64(&P.offsets[3 * o], P.a, P.k, P.eta, n_d, G);
-    float* re = &P.table[(size_t)o * 2 * plane];
-    float* im = re + plane;
-    for (int u = 0; u < P.nu; ++u)
-      for (int v = 0; v < P.nu; ++v) {
-        re[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].real();
-        im[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].imag();
-      }
+  if (!P.split()) {
+    const size_t plane = P.plane_floats();
+    P.table.assign((size_t)n_off * 2 * plane, 0.0f);
+    for (int64_t o = 0; o < n_off; ++o) {
+      operator_fp64(&P.offsets[3 * o], P.a, P.k, P.eta, n_d, G);
+      float* re = &P.table[(size_t)o * 2 * plane];
+      float* im = re + plane;
+      for (int u = 0; u < P.nu; ++u)
+        for (int v = 0; v < P.nu; ++v) {
+          re[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].real();
+          im[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].imag();
+        }
+    }
+  } else {
+    // G (rounded to FP32 first, like the FP32 path) = hi + lo, hi = bf16(G),
+    // lo = bf16(G - hi). Planes per offset: re.hi, re.lo, im.hi, im.lo.
+    const size_t plane = (size_t)P.nu * P.khb;
+    P.table_bf16.assign((size_t)n_off * 4 * plane, 0);
+    for (int64_t o = 0; o < n_off; ++o) {
+      operator_fp64(&P.offsets[3 * o], P.a, P.k, P.eta, n_d, G);
+      uint16_t* base = &P.table_bf16[(size_t)o * 4 * plane];
+      for (int u = 0; u < P.nu; ++u)
+        for (int v = 0; v < P.nu; ++v) {
+          const std::complex<double> g = G[(size_t)u * P.nu + v];
+          const float parts[2] = {(float)g.real(), (float)g.imag()};
+          for (int c = 0; c < 2; ++c) {
+            const uint16_t hi = bf16_bits(parts[c]);
+            const uint16_t lo = bf16_bits(parts[c] - bf16_value(hi));
+            base[(2 * c) * plane + (size_t)u * P.khb + v] = hi;
+            base[(2 * c + 1) * plane + (size_t)u * P.khb + v] = lo;
+          }
+        }
+    }
   }
   return std::string();
 }

@@ -6,6 +6,7 @@
 #include <complex>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,24 @@ constexpr int kTranslateGroups = 512;
 // of 4. A box vector is stored as [re(N_u), 0 pad | im(N_u), 0 pad], 2*kh
 // floats, so both halves start 16-byte aligned.
 inline int half_len(int nu) { return (nu + 3) & ~3; }
+
+// Split-precision layouts (BF16 hi/lo): half-length rounded up to a
+// multiple of 8 so a lane's 8 consecutive BF16 values are one 16-byte read.
+inline int half_len_bf16(int nu) { return (nu + 7) & ~7; }
+
+// Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
+inline uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+inline float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
 
 // Free-space dyadic Green's function of Eq. (5)-(6), FP64, time
 // convention exp(+j omega t): D(R) = psi(R) { I (1 - j/kR - 1/(kR)^2)
@@ -56,8 +75,12 @@ struct Plan {
   int32_t n_orbits = 0;
 
   // Operator table image: per offset two planes (re, im) of nu rows of kh
-  // floats; columns >= nu are zero.
+  // floats; columns >= nu are zero. Split precision instead stores, per
+  // offset, planes (re, im) x (hi, lo) of nu rows of khb BF16 values.
   std::vector<float> table;
+  std::vector<uint16_t> table_bf16;
+  int khb = 0;
+  bool split() const { return precision == 1; }
 
   int64_t n_pairs() const { return (int64_t)pair_src.size(); }
   int32_t n_off() const { return (int32_t)(offsets.size() / 3); }
@@ -65,7 +88,13 @@ struct Plan {
   int32_t n_groups() const { return (int32_t)wg_ptr.size() - 1; }
   size_t plane_floats() const { return (size_t)nu * kh; }
   size_t op_floats() const { return 2 * plane_floats(); }
-  int pstride() const { return 2 * kh; }
+  int pstride() const { return 2 * kh; }              // partial rows, floats
+  // Box vectors of stage 1 -> 2, in floats: FP32 [re | im] halves, or in
+  // split mode [re: hi, lo | im: hi, lo] BF16 runs of khb values.
+  int vstride() const { return split() ? 2 * khb : 2 * kh; }
+  size_t table_bytes() const {
+    return split() ? table_bf16.size() * sizeof(uint16_t) : table.size() * sizeof(float);
+  }
 
   // Binding.
   char* ws = nullptr;

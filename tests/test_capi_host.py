@@ -177,3 +177,18 @@ def test_sparse_coordinates_use_hash_index():
         assert sorted(zip(t, s)) == sorted(zip(j, i))
     finally:
         U.plan_destroy(plan)
+
+
+def test_split_precision_plan():
+    b = W.grid_boxes(4, 4, 4)
+    plan = U.plan_create(b, A, K, 3, "ilist", precision="split-bf16")
+    try:
+        info = U.plan_info(plan)
+        assert info["precision"] == U.SPLIT_BF16
+        # four BF16 planes of 81 x 88 per offset
+        assert info["table_bytes"] == info["n_offsets"] * 4 * 81 * 88 * 2
+    finally:
+        U.plan_destroy(plan)
+    with pytest.raises(U.UbfError) as e:
+        U.plan_create(b, A, K, 4, "ilist", precision="split-bf16")
+    assert "split precision" in str(e.value)
