@@ -14,6 +14,11 @@ three products, FP32 accumulation), which stays within the 1e-4 relative
 error of the plain FP32 form; the plain FP32 form is timed after it and
 reported under "compare" with the speedup.
 
+``--workload 4`` times the batching workload instead: 64 scatterers of
+200 to 20k boxes, four right-hand sides each, in one plan, one captured HIP
+graph of three kernels per step (20 steps by default); a step counts
+64 x 4 MVMs.
+
 Prints one JSON line with the throughput, latency percentiles, the
 roofline position of the dominant kernel (timed with HIP events on the
 stream it runs on) and the FP64 CPU oracle timed on a bounded sample,
@@ -93,12 +98,13 @@ def measured_traffic(stage):
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    argv = sys.argv[1:]
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--basis", choices=["synthetic", "identity"], default="synthetic")
-    ap.add_argument("--workload", type=int, default=2,
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4],
                     help="synthetic workload index (2 = 3,338-box shell)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle sample")
@@ -113,7 +119,10 @@ def parse():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing "
                          "(reference kernel for scaling hardware byte counters)")
-    return ap.parse_args()
+    args = ap.parse_args(argv)
+    args.steps_given = any(a.startswith("--steps") for a in argv)
+    args.warmup_given = any(a.startswith("--warmup") for a in argv)
+    return args
 
 
 def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
@@ -208,6 +217,158 @@ def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0):
     return out
 
 
+def batch_form(U, W, torch, w, precision, warmup, steps):
+    """One batched plan over all scatterers of `w` (identity basis, w.nrhs
+    right-hand sides each): tune the stage-2 grid, time eager calls per
+    stage, then time `steps` replays of the captured graph."""
+    import numpy as np
+
+    parts = w.extra["scatterers"]
+    nrhs = w.nrhs
+    t0 = time.perf_counter()
+    ff = U.FarField(None, w.a, w.k, w.n_d, w.far_mode, max_nrhs=nrhs,
+                    precision=precision, scatterers=parts)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    groups = ff.tune(nrhs=nrhs, reps=2)
+    x = torch.from_numpy(w.coefficients()).to("cuda:0")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(2):
+        U.far_mvm(ff.plan, x, y, nrhs, stream)
+    n_prof = max(3, min(steps, 10))
+    U.profile_begin(ff.plan, n_prof)
+    for _ in range(n_prof):
+        U.far_mvm(ff.plan, x, y, nrhs, stream)
+    stage_ms, _ = U.profile_end(ff.plan, n_prof)
+    ff.capture(x, y)
+    for _ in range(warmup):
+        ff.replay()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        ff.replay()
+        b.record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    call_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    out = {"info": ff.info, "plan_ms": plan_ms, "dt": dt, "groups": groups,
+           "value": steps * nrhs * len(parts) / dt, "avg_us": stage_ms / n_prof * 1e3,
+           "call_ms": call_ms, "y": y.cpu().numpy(), "x": x.cpu().numpy()}
+    ff.close()
+    return out
+
+
+def batch_cpu_baseline(w, x, y_gpu, budget_s, n_pairs_total):
+    """The oracle on whole scatterers (smallest first) until the budget is
+    spent; its rate is scaled to the whole batch by far-pair count, which
+    sets the oracle's cost."""
+    import numpy as np
+    import oracle as O
+
+    parts = w.extra["scatterers"]
+    offs = np.cumsum([0] + [len(b) for b in parts]) * w.n_u
+    order = np.argsort([len(b) for b in parts])
+    done, pairs_done, t_used, errs = 0, 0, 0.0, []
+    for s in order:
+        b = parts[s]
+        sl = slice(offs[s], offs[s + 1])
+        t0 = time.perf_counter()
+        ref = O.far_mvm(x[:, sl].astype(np.complex128), b, w.a, w.k, w.n_d,
+                        mode=w.far_mode)
+        t_used += time.perf_counter() - t0
+        j, _, _ = O.far_pairs(b, O.FAR_ILIST if w.far_mode == "ilist" else O.FAR_FULL)
+        pairs_done += len(j)
+        done += 1
+        errs.append(float(np.linalg.norm(y_gpu[:, sl] - ref) / np.linalg.norm(ref)))
+        if t_used >= budget_s:
+            break
+    est_total_s = t_used * n_pairs_total / max(pairs_done, 1)
+    cores = len(os.sched_getaffinity(0))
+    return ({"value": w.nrhs * len(parts) / est_total_s, "unit": "MVM/s", "cores": cores,
+             "kind": "oracle",
+             "sample": (f"{done} whole scatterers (smallest first, {pairs_done} far pairs, "
+                        f"{w.nrhs} RHS each) in {t_used:.1f} s, scaled to the batch's "
+                        f"{n_pairs_total} far pairs (NumPy FP64, {cores} host cores "
+                        f"visible, {cpu_model()})")},
+            max(errs))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def bench_batch(args, U, W, torch):
+    import numpy as np
+
+    w = W.config(4)
+    chosen = args.precision
+    steps = args.steps if args.steps_given else 20
+    warmup = args.warmup if args.warmup_given else 3
+    res = batch_form(U, W, torch, w, chosen, warmup, steps)
+    other = None
+    if not args.no_compare:
+        other = batch_form(U, W, torch, w, "fp32" if chosen != "fp32" else "split-bf16",
+                           warmup, steps)
+    info, avg_us = res["info"], res["avg_us"]
+    n_pairs, n_box, nu, nrhs = info["n_pairs"], info["n_boxes"], info["n_u"], w.nrhs
+    split = chosen == "split-bf16"
+    flops = info["translate_flops"] * nrhs
+    khb = (nu + 7) // 8 * 8
+    issued = 3 * 2 * (-(-2 * nu // 32) * 32) * (2 * khb) * n_pairs * nrhs
+    ach = (issued if split else flops) / (avg_us[1] * 1e-6) / 1e12
+    peak = PEAK_BF16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
+    box_bytes = nrhs * n_box * nu * 8
+    stages = {"aggregate": {"avg_us": float(avg_us[0]), "algorithmic_bytes": 2 * box_bytes},
+              "translate": {"avg_us": float(avg_us[1]), "algorithmic_flops": flops,
+                            "tflops": flops / (avg_us[1] * 1e-6) / 1e12,
+                            "issued_flops": issued if split else flops},
+              "disaggregate": {"avg_us": float(avg_us[2]),
+                               "algorithmic_bytes": 2 * box_bytes}}
+    kinds = w.extra["kinds"]
+    out = {
+        "metric": "far-zone MVMs/s", "value": res["value"], "unit": "MVM/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": res["dt"] / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (stage 2 bf16 hi/lo x3, f32 accumulation)" if split else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "scatterers": len(kinds),
+                   "kinds": {k: kinds.count(k) for k in sorted(set(kinds))},
+                   "n_boxes": n_box, "n_pairs": n_pairs, "n_u": nu,
+                   "far_mode": w.far_mode, "basis": "identity", "nrhs": nrhs,
+                   "precision": chosen, "launch": "one HIP graph (3 kernels) per step",
+                   "translate_groups": res["groups"]},
+        "p50_ms": float(np.percentile(res["call_ms"], 50)),
+        "p99_ms": float(np.percentile(res["call_ms"], 99)),
+        "plan_ms": res["plan_ms"], "stages": stages,
+        "roofline": {"kernel": "translate_split" if split else "translate_mfma",
+                     "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None},
+    }
+    if other is not None:
+        out["compare"] = {"precision": "fp32" if chosen != "fp32" else "split-bf16",
+                          "value": other["value"],
+                          "translate_us": float(other["avg_us"][1]),
+                          "speedup_of_chosen": res["value"] / other["value"],
+                          "rel_l2_diff_vs_chosen": float(np.linalg.norm(other["y"] - res["y"])
+                                                         / np.linalg.norm(other["y"]))}
+    if not args.no_cpu_baseline:
+        cb, err = batch_cpu_baseline(w, res["x"], res["y"], args.cpu_seconds, n_pairs)
+        out["cpu_baseline"] = cb
+        out["rel_l2_vs_oracle_sampled_scatterers_max"] = err
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -225,6 +386,8 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload == 4:
+        return bench_batch(args, U, W, torch)
     w = W.config(args.workload)
     nrhs = args.nrhs
     chosen = args.precision

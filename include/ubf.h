@@ -105,6 +105,8 @@ typedef struct ubf_info {
   double translate_flops;   /* real flops per RHS: 8 * n_u^2 * n_pairs */
   int32_t mfma;             /* 1 if stage 2 runs on the matrix cores */
   int32_t precision;        /* enum ubf_precision of the plan */
+  int32_t n_scatterers;     /* independent scatterers in the plan (>= 1) */
+  int32_t translate_groups; /* persistent stage-2 workgroups per RHS */
 } ubf_info;
 
 typedef struct ubf_plan ubf_plan;
@@ -119,6 +121,27 @@ typedef struct ubf_plan ubf_plan;
  * beyond 2^31-1 pairs;
  * UBF_ENOMEM if host memory runs out. *out is set only on success. */
 int ubf_plan_create(const ubf_problem* problem, ubf_plan** out);
+
+/* One plan over many independent scatterers, run together by every compute
+ * entry point (batching). problem->box_ijk holds the boxes of all
+ * scatterers concatenated (problem->n_boxes in total); boxes
+ * [scatterer_ptr[s], scatterer_ptr[s+1]) form scatterer s. All scatterers
+ * share a, k, eta, n_d, far_mode and precision, hence one operator table
+ * over the union of their offsets (an operator depends only on the
+ * integer offset, Sec. 2.2). The far set (Algorithm 2) is built within
+ * each scatterer: no pair joins two scatterers, and coordinates may repeat
+ * across scatterers (each has its own origin, which the ILIST parent rule
+ * floor(c/2) uses). Box vectors and x, y follow the concatenated box
+ * order, so y restricted to scatterer s equals the product of a plan made
+ * from scatterer s alone.
+ * scatterer_ptr: host, n_scatterers+1 values, scatterer_ptr[0] = 0,
+ * strictly increasing, scatterer_ptr[n_scatterers] = n_boxes; copied.
+ * Errors: those of ubf_plan_create, plus UBF_EINVAL for a null
+ * scatterer_ptr, n_scatterers < 1, an empty scatterer or a last value
+ * other than n_boxes; duplicate coordinates are rejected within a
+ * scatterer only. */
+int ubf_plan_create_batch(const ubf_problem* problem, int32_t n_scatterers,
+                          const int64_t* scatterer_ptr, ubf_plan** out);
 
 /* Device workspace bytes needed to run up to max_nrhs right-hand sides
  * per call (operator table, index tables, internal vectors). Returns 0 for
@@ -157,6 +180,32 @@ int ubf_plan_set_basis(ubf_plan* plan, const int64_t* nb_ptr,
  * of range), UBF_ESTATE (unbound), UBF_EDEVICE (launch failed). */
 int ubf_far_mvm(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs,
                 void* hip_stream);
+
+/* Record the whole product y = T G S x for these d_x, d_y and nrhs as a
+ * HIP graph owned by the plan (the three stage launches, no memory
+ * operations), replacing any earlier one. Nothing runs at capture; the
+ * capture uses a stream of the plan's own. The graph holds the pointers it
+ * was captured with and the plan's workspace addresses: ubf_plan_bind,
+ * ubf_plan_set_basis and ubf_plan_tune discard it.
+ * Errors: those of ubf_far_mvm; UBF_EDEVICE if capture or instantiation
+ * fails. */
+int ubf_plan_capture(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs);
+
+/* Launch the captured product on hip_stream (asynchronous, one graph
+ * launch for the three stages). Errors: UBF_EINVAL (null plan),
+ * UBF_ESTATE (nothing captured), UBF_EDEVICE. */
+int ubf_plan_replay(ubf_plan* plan, void* hip_stream);
+
+/* Autotune the persistent stage-2 grid of a bound plan: time `reps`
+ * translation launches for nrhs right-hand sides at each candidate
+ * workgroup count (256, 512, 1024, 2048, 4096, capped by the number of
+ * work chunks), keep the fastest, and write the chosen count to
+ * *groups_out (may be NULL). Runs and waits on hip_stream; overwrites the
+ * workspace's internal vectors (never x or y). Results of later products
+ * do not depend on the choice. Errors: UBF_EINVAL (null plan, nrhs out of
+ * 1..max_nrhs, reps out of 1..1000), UBF_ESTATE (unbound), UBF_EDEVICE. */
+int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
+                  int32_t* groups_out);
 
 /* Stage 1 alone: d_P[nrhs][n_boxes][N_u] = S_i x_i (complex64). */
 int ubf_aggregate(ubf_plan* plan, const void* d_x, void* d_P, int32_t nrhs,

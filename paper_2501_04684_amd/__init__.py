@@ -19,7 +19,8 @@ import numpy as np
 
 __all__ = [
     "UbfError", "FAR_ILIST", "FAR_FULL", "FP32", "SPLIT_BF16", "lib", "library_path",
-    "declared_symbols", "plan_create", "workspace_bytes", "plan_bind",
+    "declared_symbols", "plan_create", "plan_create_batch", "workspace_bytes",
+    "plan_bind", "plan_capture", "plan_replay", "plan_tune",
     "plan_set_basis", "far_mvm", "aggregate", "translate", "disaggregate",
     "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
     "profile_begin", "profile_end", "plan_destroy", "status_string",
@@ -60,17 +61,23 @@ class _Info(ctypes.Structure):
                 ("n_u", ctypes.c_int32), ("n_d", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("translate_flops", ctypes.c_double), ("mfma", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("n_scatterers", ctypes.c_int32),
+                ("translate_groups", ctypes.c_int32)]
 
 
 _lib = None
 _VP, _I32, _I64, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 _SIGS = {
     "ubf_plan_create": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_VP)]),
+    "ubf_plan_create_batch": (ctypes.c_int, [ctypes.POINTER(_Problem), _I32, _VP,
+                                             ctypes.POINTER(_VP)]),
     "ubf_workspace_bytes": (_SZ, [_VP, _I32]),
     "ubf_plan_bind": (ctypes.c_int, [_VP, _VP, _SZ, _I32, _VP]),
     "ubf_plan_set_basis": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ubf_far_mvm": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
+    "ubf_plan_capture": (ctypes.c_int, [_VP, _VP, _VP, _I32]),
+    "ubf_plan_replay": (ctypes.c_int, [_VP, _VP]),
+    "ubf_plan_tune": (ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
     "ubf_aggregate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
     "ubf_translate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
     "ubf_disaggregate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
@@ -154,6 +161,24 @@ def plan_create(boxes, a: float, k: float, n_d: int, far_mode="ilist",
     return out.value
 
 
+def plan_create_batch(scatterers, a: float, k: float, n_d: int, far_mode="ilist",
+                      eta: float = 0.0, precision: int = FP32):
+    """One plan over several scatterers, each an (n_s, 3) array of box
+    coordinates; their boxes are concatenated in the given order."""
+    parts = [np.asarray(b, dtype=np.int32).reshape(-1, 3) for b in scatterers]
+    b = np.ascontiguousarray(np.concatenate(parts) if parts else
+                             np.zeros((0, 3), np.int32))
+    ptr = np.zeros(len(parts) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(q) for q in parts])
+    prob = _Problem(len(b), b.ctypes.data, float(a), float(k), float(eta),
+                    int(n_d), _MODES[far_mode], _PRECISIONS[precision])
+    out = _VP()
+    _check(lib().ubf_plan_create_batch(ctypes.byref(prob), len(parts),
+                                       ptr.ctypes.data, ctypes.byref(out)),
+           "ubf_plan_create_batch")
+    return out.value
+
+
 def workspace_bytes(plan, max_nrhs: int) -> int:
     return int(lib().ubf_workspace_bytes(plan, int(max_nrhs)))
 
@@ -184,6 +209,25 @@ def _nrhs(x, nrhs):
 def far_mvm(plan, x, y, nrhs=None, stream=None):
     _check(lib().ubf_far_mvm(plan, _dev_ptr(x), _dev_ptr(y), _nrhs(x, nrhs),
                              _stream(stream)), "ubf_far_mvm")
+
+
+def plan_capture(plan, x, y, nrhs=None):
+    """Record y = T G S x (these tensors, this nrhs) as the plan's HIP graph."""
+    _check(lib().ubf_plan_capture(plan, _dev_ptr(x), _dev_ptr(y), _nrhs(x, nrhs)),
+           "ubf_plan_capture")
+
+
+def plan_replay(plan, stream=None):
+    """Launch the captured product on the stream (default: torch's current)."""
+    _check(lib().ubf_plan_replay(plan, _stream(stream)), "ubf_plan_replay")
+
+
+def plan_tune(plan, nrhs: int = 1, reps: int = 5, stream=None) -> int:
+    """Autotune the persistent stage-2 grid; returns the chosen group count."""
+    g = ctypes.c_int32(0)
+    _check(lib().ubf_plan_tune(plan, int(nrhs), int(reps), _stream(stream),
+                               ctypes.byref(g)), "ubf_plan_tune")
+    return g.value
 
 
 def aggregate(plan, x, P, nrhs=None, stream=None):
@@ -258,12 +302,19 @@ class FarField:
 
     ``FarField(boxes, a, k, n_d)(x)`` returns ``y = T G S x`` for a complex64
     CUDA tensor ``x`` of shape [nrhs, sum N_b] (or [sum N_b]).
+
+    ``scatterers`` (a list of box arrays) replaces ``boxes`` to batch several
+    independent scatterers in one plan.
     """
 
     def __init__(self, boxes, a, k, n_d, far_mode="ilist", eta=0.0,
-                 max_nrhs=1, device="cuda", precision=FP32):
+                 max_nrhs=1, device="cuda", precision=FP32, scatterers=None):
         import torch
-        self.plan = plan_create(boxes, a, k, n_d, far_mode, eta, precision)
+        if scatterers is not None:
+            self.plan = plan_create_batch(scatterers, a, k, n_d, far_mode, eta,
+                                          precision)
+        else:
+            self.plan = plan_create(boxes, a, k, n_d, far_mode, eta, precision)
         self.info = plan_info(self.plan)
         self.max_nrhs = int(max_nrhs)
         nbytes = workspace_bytes(self.plan, self.max_nrhs)
@@ -287,6 +338,20 @@ class FarField:
         y = torch.empty_like(x2) if out is None else out
         far_mvm(self.plan, x2, y, x2.shape[0], stream)
         return y.reshape(x.shape) if out is None else y
+
+    def tune(self, nrhs=None, reps=5):
+        g = plan_tune(self.plan, self.max_nrhs if nrhs is None else nrhs, reps)
+        self.info = plan_info(self.plan)
+        return g
+
+    def capture(self, x, y):
+        """Record y = T G S x for these two tensors; run it with replay()."""
+        x2 = x.reshape(-1, self.nb_total)
+        plan_capture(self.plan, x2, y, x2.shape[0])
+        self._graph_io = (x, y)
+
+    def replay(self, stream=None):
+        plan_replay(self.plan, stream)
 
     def close(self):
         plan_destroy(self.plan)

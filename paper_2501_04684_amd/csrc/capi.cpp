@@ -18,8 +18,20 @@ struct ubf_plan {
   int32_t prof_max = 0;
   int32_t prof_n = 0;
   bool profiling = false;
+  // Captured three-stage product (ubf_plan_capture / ubf_plan_replay).
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
   ~ubf_plan() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -70,11 +82,9 @@ size_t basis_vec_bytes(const ubf::Plan& p, int32_t nrhs) {
   return (size_t)nrhs * p.nb_total() * 8;
 }
 
-}  // namespace
-
-extern "C" {
-
-int ubf_plan_create(const ubf_problem* problem, ubf_plan** out) {
+// Shared body of ubf_plan_create and ubf_plan_create_batch.
+int create(const ubf_problem* problem, const int64_t* scat_ptr, int64_t n_scat,
+           ubf_plan** out) {
   if (!problem || !out) return fail(UBF_EINVAL, "problem or out is NULL");
   ubf_plan* plan = new (std::nothrow) ubf_plan();
   if (!plan) return fail(UBF_ENOMEM, "host allocation failed");
@@ -82,7 +92,8 @@ int ubf_plan_create(const ubf_problem* problem, ubf_plan** out) {
   try {
     why = ubf::build_plan(problem->box_ijk, problem->n_boxes, problem->a,
                           problem->k, problem->eta, problem->n_d,
-                          problem->far_mode, problem->precision, plan->p);
+                          problem->far_mode, problem->precision, scat_ptr, n_scat,
+                          plan->p);
   } catch (const std::bad_alloc&) {
     delete plan;
     return fail(UBF_ENOMEM, "host allocation failed while building the plan");
@@ -96,6 +107,37 @@ int ubf_plan_create(const ubf_problem* problem, ubf_plan** out) {
   }
   *out = plan;
   return ok();
+}
+
+// The three stages of the product, enqueued on `s` (ev: optional events).
+int enqueue_mvm(const ubf::Plan& p, const void* d_x, void* d_y, int32_t nrhs,
+                hipStream_t s, hipEvent_t* ev) {
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  int e = ubf::launch_aggregate(p, d_x, p.d_P, nrhs, s);
+  if (e) return hip_fail(e, "aggregate launch");
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  e = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, s);
+  if (e) return hip_fail(e, "translate launch");
+  if (ev && hipEventRecord(ev[2], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  e = ubf::launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, s);
+  if (e) return hip_fail(e, "disaggregate launch");
+  if (ev && hipEventRecord(ev[3], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ubf_plan_create(const ubf_problem* problem, ubf_plan** out) {
+  return create(problem, nullptr, 0, out);
+}
+
+int ubf_plan_create_batch(const ubf_problem* problem, int32_t n_scatterers,
+                          const int64_t* scatterer_ptr, ubf_plan** out) {
+  if (!scatterer_ptr) return fail(UBF_EINVAL, "scatterer_ptr is NULL");
+  if (n_scatterers < 1) return fail(UBF_EINVAL, "n_scatterers must be >= 1");
+  return create(problem, scatterer_ptr, n_scatterers, out);
 }
 
 size_t ubf_workspace_bytes(const ubf_plan* plan, int32_t max_nrhs) {
@@ -114,6 +156,7 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
   if (bytes < L.total)
     return fail(UBF_ENOMEM, "workspace too small: need " + std::to_string(L.total) +
                                 " bytes, got " + std::to_string(bytes));
+  plan->drop_graph();
   char* ws = (char*)d_workspace;
   hipStream_t s = (hipStream_t)hip_stream;
   struct Copy {
@@ -163,6 +206,7 @@ int ubf_plan_set_basis(ubf_plan* plan, const int64_t* nb_ptr, const void* d_S,
                        const void* d_T) {
   if (!plan) return fail(UBF_EINVAL, "plan is NULL");
   ubf::Plan& p = plan->p;
+  plan->drop_graph();
   if (!nb_ptr && !d_S && !d_T) {
     if (!p.ws) return fail(UBF_ESTATE, "plan is not bound to a workspace");
     std::vector<int64_t> nb(p.n_box + 1);
@@ -197,21 +241,116 @@ int ubf_far_mvm(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs,
                       plan ? basis_vec_bytes(plan->p, nrhs) : 0,
                       plan ? basis_vec_bytes(plan->p, nrhs) : 0);
   if (st != UBF_OK) return st;
-  const ubf::Plan& p = plan->p;
   hipEvent_t* ev = nullptr;
   if (plan->profiling && plan->prof_n < plan->prof_max)
     ev = &plan->events[4 * (size_t)plan->prof_n++];
+  return enqueue_mvm(plan->p, d_x, d_y, nrhs, (hipStream_t)hip_stream, ev);
+}
+
+int ubf_plan_capture(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs) {
+  int st = check_call(plan, d_x, d_y, nrhs,
+                      plan ? basis_vec_bytes(plan->p, nrhs) : 0,
+                      plan ? basis_vec_bytes(plan->p, nrhs) : 0);
+  if (st != UBF_OK) return st;
+  plan->drop_graph();
+  hipError_t e;
+  if (!plan->cap_stream) {
+    e = hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      plan->cap_stream = nullptr;
+      return hip_fail(e, "hipStreamCreateWithFlags (capture)");
+    }
+  }
+  e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  const int launched = enqueue_mvm(plan->p, d_x, d_y, nrhs, plan->cap_stream, nullptr);
+  const std::string why = g_last_error;
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(plan->cap_stream, &g);
+  if (launched != UBF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(launched, why);
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  plan->graph = g;
+  plan->exec = x;
+  return ok();
+}
+
+int ubf_plan_replay(ubf_plan* plan, void* hip_stream) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  if (!plan->exec) return fail(UBF_ESTATE, "no captured product (ubf_plan_capture)");
+  hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
+                  int32_t* groups_out) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  ubf::Plan& p = plan->p;
+  if (!p.ws) return fail(UBF_ESTATE, "plan is not bound to a workspace");
+  if (nrhs < 1 || nrhs > p.max_nrhs)
+    return fail(UBF_EINVAL, "nrhs must be in 1..max_nrhs of the binding");
+  if (reps < 1 || reps > 1000) return fail(UBF_EINVAL, "reps must be in 1..1000");
+  plan->drop_graph();
   hipStream_t s = (hipStream_t)hip_stream;
-  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  int e = ubf::launch_aggregate(p, d_x, p.d_P, nrhs, hip_stream);
-  if (e) return hip_fail(e, "aggregate launch");
-  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  e = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, hip_stream);
-  if (e) return hip_fail(e, "translate launch");
-  if (ev && hipEventRecord(ev[2], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  e = ubf::launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, hip_stream);
-  if (e) return hip_fail(e, "disaggregate launch");
-  if (ev && hipEventRecord(ev[3], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  const ubf::Layout L = ubf::workspace_layout(p, p.max_nrhs);
+  // Column values do not change the timing; start them from zero.
+  hipError_t e = hipMemsetAsync(p.d_P, 0, L.part - L.P, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync (tune)");
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&t1)) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  auto upload = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(p.d_wg_ptr, p.wg_ptr.data(),
+                                  p.wg_ptr.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s);
+    return r != hipSuccess ? r : hipStreamSynchronize(s);
+  };
+  const int64_t before = p.n_groups();
+  int64_t best = before;
+  float best_ms = 0.f;
+  int status = UBF_OK;
+  std::string why;
+  const int64_t cands[] = {256, 512, 1024, 2048, 4096};
+  for (int64_t c : cands) {
+    ubf::partition_groups(p, c);
+    if (p.n_groups() != c && c != cands[0]) continue;  // capped by the chunk count
+    if ((e = upload()) != hipSuccess) { status = hip_fail(e, "upload (tune)"); break; }
+    int le = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, s);  // warm-up
+    if (!le && hipEventRecord(t0, s) != hipSuccess) le = (int)hipGetLastError();
+    for (int r = 0; r < reps && !le; ++r) le = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, s);
+    if (!le && hipEventRecord(t1, s) != hipSuccess) le = (int)hipGetLastError();
+    if (!le) le = (int)hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (!le) le = (int)hipEventElapsedTime(&ms, t0, t1);
+    if (le) { status = hip_fail(le, "translate (tune)"); break; }
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = p.n_groups();
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (status != UBF_OK) {
+    why = g_last_error;
+    ubf::partition_groups(p, before);
+    (void)upload();
+    return fail(status, why);
+  }
+  ubf::partition_groups(p, best);
+  if ((e = upload()) != hipSuccess) return hip_fail(e, "upload (tune)");
+  if (groups_out) *groups_out = (int32_t)p.n_groups();
   return ok();
 }
 
@@ -322,6 +461,8 @@ int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
   out->translate_flops = 8.0 * p.nu * (double)p.nu * (double)p.n_pairs();
   out->mfma = ubf::translate_uses_mfma(p) ? 1 : 0;
   out->precision = p.precision;
+  out->n_scatterers = p.n_scat();
+  out->translate_groups = p.n_groups();
   return ok();
 }
 

@@ -33,8 +33,8 @@ struct BoxIndex {
   static uint64_t key(int64_t x, int64_t y, int64_t z) {
     return (uint64_t(x) << 42) ^ (uint64_t(y) << 21) ^ uint64_t(z);
   }
-  // Returns false on a duplicate coordinate.
-  bool build(const std::vector<int32_t>& b, int64_t n) {
+  // Index boxes b[0..n) (3 coordinates each); false on a duplicate.
+  bool build(const int32_t* b, int64_t n) {
     int32_t mx = 0, my = 0, mz = 0;
     for (int64_t i = 0; i < n; ++i) {
       mx = std::max(mx, b[3 * i]);
@@ -45,6 +45,8 @@ struct BoxIndex {
     ny = my + 1;
     nz = mz + 1;
     use_dense = (int64_t)nx * ny * nz <= kDenseCells;
+    dense.clear();
+    sparse.clear();
     if (use_dense) {
       dense.assign((size_t)nx * ny * nz, -1);
       for (int64_t i = 0; i < n; ++i) {
@@ -122,6 +124,18 @@ void operator_fp64(const int32_t w[3], double a, double k, double eta, int n_d,
     }
 }
 
+// The four wavefronts of a group work on one chunk at a time, so a group's
+// time is its number of chunks whatever their fill: ranges are balanced by
+// chunk count. Trailing groups may get empty ranges.
+void partition_groups(Plan& P, int64_t groups) {
+  const int64_t nch = P.n_chunks();
+  groups = std::min<int64_t>(groups, std::max<int64_t>(nch, 1));
+  groups = std::min<int64_t>((groups + 7) / 8 * 8, kMaxTranslateGroups);
+  P.wg_ptr.assign(groups + 1, (int32_t)nch);
+  P.wg_ptr[0] = 0;
+  for (int64_t g = 1; g < groups; ++g) P.wg_ptr[g] = (int32_t)((nch * g + groups - 1) / groups);
+}
+
 Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   Layout L{};
   size_t at = 0;
@@ -132,7 +146,7 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   };
   L.table = take(p.table_bytes());
   L.chunks = take(p.chunks.size() * sizeof(int32_t));
-  L.wg_ptr = take(p.wg_ptr.size() * sizeof(int32_t));
+  L.wg_ptr = take((size_t)(kMaxTranslateGroups + 1) * sizeof(int32_t));
   L.pair_src = take(p.pair_src.size() * sizeof(int32_t));
   L.pair_dst = take(p.pair_dst.size() * sizeof(int32_t));
   L.test_ptr = take(p.test_ptr.size() * sizeof(int32_t));
@@ -146,7 +160,8 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
 
 std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
                        double k, double eta, int n_d, int far_mode,
-                       int precision, Plan& P) {
+                       int precision, const int64_t* scat_ptr, int64_t n_scat,
+                       Plan& P) {
   if (!box_ijk) return "box_ijk is NULL";
   if (n_box < 1) return "n_boxes must be >= 1";
   if (n_box > std::numeric_limits<int32_t>::max() / 2) return "n_boxes too large";
@@ -172,44 +187,59 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   P.far_mode = far_mode;
   P.precision = precision;
 
-  BoxIndex index;
-  if (!index.build(P.boxes, n_box)) return "duplicate box coordinates";
+  if (scat_ptr) {
+    if (n_scat < 1) return "n_scatterers must be >= 1";
+    if (scat_ptr[0] != 0) return "scatterer_ptr[0] must be 0";
+    for (int64_t s = 0; s < n_scat; ++s)
+      if (scat_ptr[s + 1] <= scat_ptr[s]) return "every scatterer needs at least one box";
+    if (scat_ptr[n_scat] != n_box) return "scatterer_ptr[n_scatterers] must equal n_boxes";
+    P.scat_ptr.assign(scat_ptr, scat_ptr + n_scat + 1);
+  } else {
+    P.scat_ptr = {0, n_box};
+  }
   const int32_t* b = P.boxes.data();
 
-  // Far set: (test j, source i, offset w = c_j - c_i), test-major.
+  // Far set: (test j, source i, offset w = c_j - c_i), test-major, built
+  // within each scatterer (global box indices).
   std::vector<int32_t> pj, pi;
   std::vector<std::array<int32_t, 3>> pw;
   const int64_t kMaxPairs = std::numeric_limits<int32_t>::max();
-  if (far_mode == 0) {
-    for (int64_t j = 0; j < n_box; ++j) {
-      const int64_t cx = b[3 * j], cy = b[3 * j + 1], cz = b[3 * j + 2];
-      for (int wx = -3; wx <= 3; ++wx)
-        for (int wy = -3; wy <= 3; ++wy)
-          for (int wz = -3; wz <= 3; ++wz) {
-            if (cheb(wx, wy, wz) < 2) continue;
-            const int64_t sx = cx - wx, sy = cy - wy, sz = cz - wz;
-            const int32_t i = index.find(sx, sy, sz);
-            if (i < 0) continue;
-            if (cheb(floordiv2(cx) - floordiv2(sx), floordiv2(cy) - floordiv2(sy),
-                     floordiv2(cz) - floordiv2(sz)) > 1)
-              continue;
-            pj.push_back((int32_t)j);
-            pi.push_back(i);
-            pw.push_back({wx, wy, wz});
-          }
-    }
-  } else {
-    for (int64_t j = 0; j < n_box; ++j)
-      for (int64_t i = 0; i < n_box; ++i) {
-        const int64_t wx = (int64_t)b[3 * j] - b[3 * i];
-        const int64_t wy = (int64_t)b[3 * j + 1] - b[3 * i + 1];
-        const int64_t wz = (int64_t)b[3 * j + 2] - b[3 * i + 2];
-        if (cheb(wx, wy, wz) < 2) continue;
-        if ((int64_t)pj.size() >= kMaxPairs) return "far set exceeds 2^31-1 pairs";
-        pj.push_back((int32_t)j);
-        pi.push_back((int32_t)i);
-        pw.push_back({(int32_t)wx, (int32_t)wy, (int32_t)wz});
+  BoxIndex index;
+  for (int64_t sc = 0; sc + 1 < (int64_t)P.scat_ptr.size(); ++sc) {
+    const int64_t lo = P.scat_ptr[sc], hi = P.scat_ptr[sc + 1];
+    if (!index.build(b + 3 * lo, hi - lo)) return "duplicate box coordinates";
+    if (far_mode == 0) {
+      for (int64_t j = lo; j < hi; ++j) {
+        const int64_t cx = b[3 * j], cy = b[3 * j + 1], cz = b[3 * j + 2];
+        for (int wx = -3; wx <= 3; ++wx)
+          for (int wy = -3; wy <= 3; ++wy)
+            for (int wz = -3; wz <= 3; ++wz) {
+              if (cheb(wx, wy, wz) < 2) continue;
+              const int64_t sx = cx - wx, sy = cy - wy, sz = cz - wz;
+              const int32_t il = index.find(sx, sy, sz);
+              if (il < 0) continue;
+              if (cheb(floordiv2(cx) - floordiv2(sx), floordiv2(cy) - floordiv2(sy),
+                       floordiv2(cz) - floordiv2(sz)) > 1)
+                continue;
+              if ((int64_t)pj.size() >= kMaxPairs) return "far set exceeds 2^31-1 pairs";
+              pj.push_back((int32_t)j);
+              pi.push_back((int32_t)(lo + il));
+              pw.push_back({wx, wy, wz});
+            }
       }
+    } else {
+      for (int64_t j = lo; j < hi; ++j)
+        for (int64_t i = lo; i < hi; ++i) {
+          const int64_t wx = (int64_t)b[3 * j] - b[3 * i];
+          const int64_t wy = (int64_t)b[3 * j + 1] - b[3 * i + 1];
+          const int64_t wz = (int64_t)b[3 * j + 2] - b[3 * i + 2];
+          if (cheb(wx, wy, wz) < 2) continue;
+          if ((int64_t)pj.size() >= kMaxPairs) return "far set exceeds 2^31-1 pairs";
+          pj.push_back((int32_t)j);
+          pi.push_back((int32_t)i);
+          pw.push_back({(int32_t)wx, (int32_t)wy, (int32_t)wz});
+        }
+    }
   }
   if ((int64_t)pj.size() > kMaxPairs) return "far set exceeds 2^31-1 pairs";
 
@@ -267,27 +297,7 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
       P.chunks.push_back(0);
     }
 
-  // Contiguous chunk ranges per translation workgroup, balanced by chunk
-  // count: the four wavefronts of a group work on one chunk at a time, so a
-  // group's time is its number of chunks whatever their fill. The group
-  // count is a multiple of 8 (one share per XCD); trailing groups may get
-  // empty ranges.
-  {
-    const int64_t nch = P.n_chunks();
-    int64_t groups = std::min<int64_t>(kTranslateGroups, std::max<int64_t>(nch, 1));
-    groups = (groups + 7) / 8 * 8;
-    std::vector<int64_t> cost(nch + 1, 0);
-    for (int64_t c = 0; c < nch; ++c) cost[c + 1] = cost[c] + 1;
-    const int64_t total = cost[nch];
-    P.wg_ptr.assign(groups + 1, (int32_t)nch);
-    P.wg_ptr[0] = 0;
-    int64_t c = 0;
-    for (int64_t g = 1; g < groups; ++g) {
-      const int64_t target = (total * g + groups - 1) / groups;
-      while (c < nch && cost[c] < target) ++c;
-      P.wg_ptr[g] = (int32_t)c;
-    }
-  }
+  partition_groups(P, kTranslateGroups);
 
   // Orbits under the 48 signed permutations: key = sorted |w|.
   std::vector<std::array<int32_t, 3>> keys(n_off);

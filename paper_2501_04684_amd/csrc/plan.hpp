@@ -16,6 +16,9 @@ namespace ubf {
 constexpr int kChunk = 128;
 // Translation workgroups: two resident per compute unit on 256 CUs.
 constexpr int kTranslateGroups = 512;
+// Largest persistent grid the tuner may pick (workspace room for its
+// chunk ranges is reserved at this size).
+constexpr int kMaxTranslateGroups = 4096;
 
 // Padded half-length of a planar box vector: N_u rounded up to a multiple
 // of 4. A box vector is stored as [re(N_u), 0 pad | im(N_u), 0 pad], 2*kh
@@ -58,6 +61,9 @@ struct Plan {
   // Problem.
   int64_t n_box = 0;
   std::vector<int32_t> boxes;  // 3 * n_box
+  // Independent scatterers: boxes [scat_ptr[s], scat_ptr[s+1]) form
+  // scatterer s; far-zone pairs never join two scatterers.
+  std::vector<int64_t> scat_ptr;
   double a = 0, k = 0, eta = 0;
   int n_d = 0, nu = 0, kh = 0, far_mode = 0, precision = 0;
 
@@ -86,6 +92,7 @@ struct Plan {
   int32_t n_off() const { return (int32_t)(offsets.size() / 3); }
   int64_t n_chunks() const { return (int64_t)(chunks.size() / 4); }
   int32_t n_groups() const { return (int32_t)wg_ptr.size() - 1; }
+  int32_t n_scat() const { return (int32_t)scat_ptr.size() - 1; }
   size_t plane_floats() const { return (size_t)nu * kh; }
   size_t op_floats() const { return 2 * plane_floats(); }
   int pstride() const { return 2 * kh; }              // partial rows, floats
@@ -128,8 +135,16 @@ struct Layout {
 Layout workspace_layout(const Plan& p, int32_t max_nrhs);
 
 // Validate and build; returns an empty string on success, else the reason.
+// scat_ptr (n_scat + 1 prefix offsets into the boxes) splits the boxes into
+// independent scatterers; NULL means one scatterer.
 std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
                        double k, double eta, int n_d, int far_mode,
-                       int precision, Plan& out);
+                       int precision, const int64_t* scat_ptr, int64_t n_scat,
+                       Plan& out);
+
+// Contiguous chunk ranges for `groups` persistent translation workgroups
+// (rounded up to a multiple of 8, at most kMaxTranslateGroups), balanced by
+// chunk count; rewrites p.wg_ptr.
+void partition_groups(Plan& p, int64_t groups);
 
 }  // namespace ubf

@@ -18,7 +18,7 @@ A, K = 0.25, 2 * np.pi
 def test_library_exports_every_declared_symbol():
     L = U.lib()
     names = U.declared_symbols()
-    assert len(names) == 17
+    assert len(names) == 21
     for name in names:
         assert hasattr(L, name), name
 
@@ -192,3 +192,111 @@ def test_split_precision_plan():
     with pytest.raises(U.UbfError) as e:
         U.plan_create(b, A, K, 4, "ilist", precision="split-bf16")
     assert "split precision" in str(e.value)
+
+
+def _small_scatterers():
+    return [b for _, b in W.scatterer_set(6, seed=11, lo=40, hi=300)]
+
+
+def test_batch_far_set_is_union_of_solo_far_sets():
+    parts = _small_scatterers()
+    plan = U.plan_create_batch(parts, A, K, 3)
+    try:
+        info = U.plan_info(plan)
+        assert info["n_scatterers"] == len(parts)
+        assert info["n_boxes"] == sum(len(b) for b in parts)
+        t, s, o = U.plan_far_pairs(plan)
+        offs = U.plan_offsets(plan)
+        got = set(zip(t.tolist(), s.tolist(), map(tuple, offs[o].tolist())))
+        want = set()
+        base = 0
+        union_offsets = set()
+        for b in parts:
+            # the oracle's far set of this scatterer alone, shifted to the
+            # batch numbering
+            j, i, w = O.far_pairs(b, O.FAR_ILIST)
+            want |= set(zip((j + base).tolist(), (i + base).tolist(), map(tuple, w.tolist())))
+            union_offsets |= set(map(tuple, w.tolist()))
+            base += len(b)
+        assert got == want
+        assert set(map(tuple, offs.tolist())) == union_offsets
+        # no pair joins two scatterers
+        ptr = np.cumsum([0] + [len(b) for b in parts])
+        assert (np.searchsorted(ptr, t, "right") == np.searchsorted(ptr, s, "right")).all()
+    finally:
+        U.plan_destroy(plan)
+
+
+def test_batch_matches_solo_plans_pair_for_pair():
+    parts = _small_scatterers()
+    plan = U.plan_create_batch(parts, A, K, 3, far_mode="full")
+    base = 0
+    try:
+        t, s, o = U.plan_far_pairs(plan)
+        offs = U.plan_offsets(plan)
+        for b in parts:
+            solo = U.plan_create(b, A, K, 3, far_mode="full")
+            try:
+                ts, ss, os_ = U.plan_far_pairs(solo)
+                sel = (t >= base) & (t < base + len(b))
+                got = sorted(zip((t[sel] - base).tolist(), (s[sel] - base).tolist(),
+                                 map(tuple, offs[o[sel]].tolist())))
+                so = U.plan_offsets(solo)
+                want = sorted(zip(ts.tolist(), ss.tolist(), map(tuple, so[os_].tolist())))
+                assert got == want
+            finally:
+                U.plan_destroy(solo)
+            base += len(b)
+    finally:
+        U.plan_destroy(plan)
+
+
+def test_batch_repeated_coordinates_across_scatterers():
+    g = W.grid_boxes(4, 4, 4)
+    plan = U.plan_create_batch([g, g, g], A, K, 2)
+    try:
+        info = U.plan_info(plan)
+        solo = U.plan_create(g, A, K, 2)
+        assert info["n_pairs"] == 3 * U.plan_info(solo)["n_pairs"]
+        U.plan_destroy(solo)
+    finally:
+        U.plan_destroy(plan)
+
+
+@pytest.mark.parametrize("ptr,msg", [
+    ([0, 0, 8], "at least one box"),
+    ([0, 4, 7], "must equal n_boxes"),
+    ([1, 4, 8], "scatterer_ptr[0]"),
+    ([0, 5, 4, 8], "at least one box"),
+])
+def test_batch_rejects_bad_scatterer_ptr(ptr, msg):
+    b = np.ascontiguousarray(W.grid_boxes(2, 2, 2))
+    prob = U._Problem(len(b), b.ctypes.data, A, K, 0.0, 3, 0, 0)
+    p = np.asarray(ptr, dtype=np.int64)
+    out = ctypes.c_void_p()
+    st = U.lib().ubf_plan_create_batch(ctypes.byref(prob), len(p) - 1, p.ctypes.data,
+                                       ctypes.byref(out))
+    assert st == -1 and msg in U.last_error() and not out.value
+    st = U.lib().ubf_plan_create_batch(ctypes.byref(prob), 2, None, ctypes.byref(out))
+    assert st == -1 and "scatterer_ptr" in U.last_error()
+
+
+def test_batch_duplicate_within_one_scatterer_rejected():
+    g = W.grid_boxes(2, 2, 2)
+    with pytest.raises(U.UbfError, match="duplicate"):
+        U.plan_create_batch([g, np.concatenate([g, g[:1]])], A, K, 3)
+
+
+def test_graph_and_tune_need_a_bound_plan():
+    plan = U.plan_create(W.grid_boxes(4, 4, 4), A, K, 3)
+    try:
+        L = U.lib()
+        assert L.ubf_plan_replay(plan, None) == -4
+        assert "no captured" in U.last_error()
+        assert L.ubf_plan_tune(plan, 1, 3, None, None) == -4
+        assert L.ubf_plan_capture(plan, 16, 1 << 20, 1) == -4
+        assert L.ubf_plan_replay(None, None) == -1
+        info = U.plan_info(plan)
+        assert info["translate_groups"] % 8 == 0 and info["n_scatterers"] == 1
+    finally:
+        U.plan_destroy(plan)

@@ -24,6 +24,8 @@ __all__ = [
     "shell_boxes",
     "plate_boxes",
     "mask_boxes",
+    "hollow_cube_boxes",
+    "scatterer_set",
     "complex_normal",
     "random_basis",
     "config",
@@ -80,6 +82,49 @@ def mask_boxes(n_target: int, rho: float, seed: int) -> np.ndarray:
     if not keep.any():
         keep[rng.integers(len(c))] = True
     return c[keep]
+
+
+def hollow_cube_boxes(n: int) -> np.ndarray:
+    """The one-box-thick surface of an ``n x n x n`` cube of boxes."""
+    c = grid_boxes(n, n, n)
+    on = ((c == 0) | (c == n - 1)).any(axis=1)
+    return c[on]
+
+
+SCATTERER_KINDS = ("shell", "hollow_cube", "plate", "mask")
+
+
+def scatterer_set(count: int, seed: int, lo: int = 200, hi: int = 20000,
+                  a: float = 0.25) -> list[tuple[str, np.ndarray]]:
+    """``count`` independent scatterers of uneven size for batched runs.
+
+    Target box counts are log-uniform in ``[lo, hi]``; kinds cycle through
+    one-box-thick spherical shells, hollow cubes, plates one or two boxes
+    thick with aspect ratio in [1, 4], and Bernoulli(rho) occupancy masks
+    with rho uniform in [0.1, 1.0]. Each scatterer has its own coordinates
+    (they may overlap across scatterers). Returns ``[(kind, boxes), ...]``.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(count):
+        target = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        kind = SCATTERER_KINDS[s % len(SCATTERER_KINDS)]
+        if kind == "shell":
+            radius = a * math.sqrt(target / (4.0 * math.pi))
+            b = shell_boxes(radius, a, a)
+        elif kind == "hollow_cube":
+            b = hollow_cube_boxes(max(2, int(round(math.sqrt(target / 6.0))) + 1))
+        elif kind == "plate":
+            thick = int(rng.integers(1, 3))
+            ratio = rng.uniform(1.0, 4.0)
+            nx = max(1, int(round(math.sqrt(target / thick * ratio))))
+            ny = max(1, int(round(target / thick / nx)))
+            b = grid_boxes(nx, ny, thick)
+        else:
+            rho = rng.uniform(0.1, 1.0)
+            b = mask_boxes(int(round(target)), rho, int(rng.integers(1 << 31)))
+        out.append((kind, b))
+    return out
 
 
 def complex_normal(shape, seed: int, dtype=np.complex64) -> np.ndarray:
@@ -146,6 +191,10 @@ def config(idx: int, **over) -> Workload:
     2: spherical shell, radius 4, thickness 0.25, a = 0.25 (centre rule).
     3: the same shell at a = 0.125 (and ``variant="plate"``: a 0.5 x 2 x 8
        plate at a = 0.125).
+    4: batching: 64 scatterers of 200 to 20k boxes (``scatterer_set``) at
+       a = 0.25, four right-hand sides each; ``boxes`` is their
+       concatenation and ``extra["scatterers"]`` the list of box arrays
+       (``count=`` picks another number of scatterers).
     """
     if idx == 1:
         w = Workload("grid6_a0.25", grid_boxes(6, 6, 6), 0.25, TWO_PI, 3,
@@ -162,6 +211,13 @@ def config(idx: int, **over) -> Workload:
             w = Workload("shell_r4_t0.25_a0.125",
                          shell_boxes(4.0, 0.25, 0.125), 0.125, TWO_PI, 3,
                          "ilist", seed=3)
+    elif idx == 4:
+        count = int(over.pop("count", 64))
+        parts = scatterer_set(count, seed=4)
+        w = Workload(f"batch{count}_a0.25", np.concatenate([b for _, b in parts]),
+                     0.25, TWO_PI, 3, "ilist", nrhs=4, seed=4,
+                     extra={"scatterers": [b for _, b in parts],
+                            "kinds": [k for k, _ in parts]})
     else:
         raise ValueError(f"unknown workload {idx}")
     for key, v in over.items():
@@ -169,4 +225,4 @@ def config(idx: int, **over) -> Workload:
     return w
 
 
-CONFIGS = (1, 2, 3)
+CONFIGS = (1, 2, 3, 4)
