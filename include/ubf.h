@@ -220,6 +220,71 @@ int ubf_translate(ubf_plan* plan, const void* d_P, void* d_E, int32_t nrhs,
 int ubf_disaggregate(ubf_plan* plan, const void* d_E, void* d_y,
                      int32_t nrhs, void* hip_stream);
 
+/* ------------------------------------------------------------------ */
+/* Iterative solution (Algorithm 5's solver loop): restarted GMRES for
+ * (sigma I + Z^F) x = b, Z^F = T G S the far-zone product of a bound plan
+ * (the near-field part Z^N needs meshes, so a complex shift sigma stands in
+ * for it). nrhs right-hand sides run as independent Krylov processes whose
+ * products share each ubf_far_mvm launch. Krylov vectors are complex64 (the
+ * product's input); every inner product, norm and Gram-Schmidt update is
+ * accumulated in FP64 (two classical passes), and the Hessenberg matrix,
+ * Givens rotations and least-squares solve are FP64, all on the device.
+ * Sums use a fixed block count and order, so runs repeat bit for bit.
+ * A right-hand side stops updating once its residual estimate
+ * ||b - A x|| / ||b|| (the rotated least-squares residual) reaches tol. */
+typedef struct ubf_gmres ubf_gmres;
+
+typedef struct ubf_gmres_status {
+  int32_t ready;       /* 1 if the last enqueued step has completed */
+  int32_t done;        /* every right-hand side converged, or max_steps reached */
+  int32_t converged;   /* every right-hand side within tol */
+  int32_t steps;       /* Arnoldi steps enqueued (one product each) */
+  int32_t restarts;    /* restarts enqueued (one extra product each) */
+  int32_t reserved;
+  double max_rel_res;  /* largest residual estimate over the right-hand sides */
+} ubf_gmres_status;
+
+/* Device workspace bytes of a solver for nrhs (1..64) right-hand sides and
+ * restart length 1..128 on this plan (0 if out of range): the restart+1
+ * Krylov blocks [nrhs][sum N_b] complex64 dominate. */
+size_t ubf_gmres_workspace_bytes(const ubf_plan* plan, int32_t nrhs, int32_t restart);
+
+/* Create a solver on a bound plan (whose max_nrhs >= nrhs) in a caller-owned
+ * 256-byte aligned device workspace. sigma = sigma_re + j sigma_im; tol in
+ * (0, 1) bounds the relative residual; max_steps caps the Arnoldi steps.
+ * The solver allocates only a small pinned host block for its status. While
+ * it runs, the plan is in use on the solver's stream. Errors: UBF_EINVAL,
+ * UBF_ESTATE (unbound plan), UBF_ENOMEM (workspace too small), UBF_EDEVICE. */
+int ubf_gmres_create(ubf_plan* plan, int32_t nrhs, int32_t restart, double sigma_re,
+                     double sigma_im, double tol, int32_t max_steps, void* d_workspace,
+                     size_t bytes, ubf_gmres** out);
+
+/* Begin a solve from x_0 = 0: d_b and d_x are [nrhs][sum N_b] complex64,
+ * not overlapping; x is written by ubf_gmres_finish (and at restarts).
+ * Enqueued on hip_stream. Errors: UBF_EINVAL, UBF_ESTATE, UBF_EDEVICE. */
+int ubf_gmres_start(ubf_gmres* solver, const void* d_b, void* d_x, void* hip_stream);
+
+/* Enqueue one Arnoldi step (one product, orthogonalisation, rotation); when
+ * the cycle is full, also the restart (x += V y, one more product for the
+ * new residual). Never waits. Errors: UBF_ESTATE (not started, finished,
+ * plan unbound or basis changed), UBF_EDEVICE. */
+int ubf_gmres_step(ubf_gmres* solver, void* hip_stream);
+
+/* Status of the last enqueued step: with wait = 0 it returns at once
+ * (out->ready = 0 while that step is still running), else it waits for it.
+ * rel_res (may be NULL) receives nrhs residual estimates.
+ * Errors: UBF_EINVAL (null), UBF_ESTATE (not started), UBF_EDEVICE. */
+int ubf_gmres_poll(ubf_gmres* solver, int32_t wait, ubf_gmres_status* out,
+                   double* rel_res);
+
+/* Complete the solution: x += V y over the current cycle. The solver must be
+ * started again before further steps. Errors: as ubf_gmres_step. */
+int ubf_gmres_finish(ubf_gmres* solver, void* hip_stream);
+
+/* Release the solver (its pinned status block; the workspace stays the
+ * caller's). */
+void ubf_gmres_destroy(ubf_gmres* solver);
+
 /* Plan sizes and work counts. Errors: UBF_EINVAL for null pointers. */
 int ubf_plan_info(const ubf_plan* plan, ubf_info* out);
 

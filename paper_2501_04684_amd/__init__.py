@@ -24,7 +24,8 @@ __all__ = [
     "plan_set_basis", "far_mvm", "aggregate", "translate", "disaggregate",
     "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
     "profile_begin", "profile_end", "plan_destroy", "status_string",
-    "last_error", "FarField",
+    "last_error", "FarField", "gmres_workspace_bytes", "gmres_create", "gmres_start",
+    "gmres_step", "gmres_poll", "gmres_finish", "gmres_destroy", "Solver",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +66,13 @@ class _Info(ctypes.Structure):
                 ("translate_groups", ctypes.c_int32)]
 
 
+class _GmresStatus(ctypes.Structure):
+    _fields_ = [("ready", ctypes.c_int32), ("done", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_rel_res", ctypes.c_double)]
+
+
 _lib = None
 _VP, _I32, _I64, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 _SIGS = {
@@ -87,6 +95,15 @@ _SIGS = {
     "ubf_plan_operator": (ctypes.c_int, [_VP, _I32, _VP]),
     "ubf_profile_begin": (ctypes.c_int, [_VP, _I32]),
     "ubf_profile_end": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ubf_gmres_workspace_bytes": (_SZ, [_VP, _I32, _I32]),
+    "ubf_gmres_create": (ctypes.c_int, [_VP, _I32, _I32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _I32, _VP, _SZ,
+                                        ctypes.POINTER(_VP)]),
+    "ubf_gmres_start": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ubf_gmres_step": (ctypes.c_int, [_VP, _VP]),
+    "ubf_gmres_poll": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(_GmresStatus), _VP]),
+    "ubf_gmres_finish": (ctypes.c_int, [_VP, _VP]),
+    "ubf_gmres_destroy": (None, [_VP]),
     "ubf_plan_destroy": (None, [_VP]),
     "ubf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ubf_last_error": (ctypes.c_char_p, []),
@@ -295,6 +312,49 @@ def plan_destroy(plan):
         lib().ubf_plan_destroy(plan)
 
 
+# ----------------------------------------------------------------- GMRES
+
+def gmres_workspace_bytes(plan, nrhs: int, restart: int) -> int:
+    return int(lib().ubf_gmres_workspace_bytes(plan, int(nrhs), int(restart)))
+
+
+def gmres_create(plan, nrhs, restart, sigma, tol, max_steps, workspace, nbytes):
+    out = _VP()
+    sigma = complex(sigma)
+    _check(lib().ubf_gmres_create(plan, int(nrhs), int(restart), sigma.real, sigma.imag,
+                                  float(tol), int(max_steps), _dev_ptr(workspace),
+                                  int(nbytes), ctypes.byref(out)), "ubf_gmres_create")
+    return out.value
+
+
+def gmres_start(solver, b, x, stream=None):
+    _check(lib().ubf_gmres_start(solver, _dev_ptr(b), _dev_ptr(x), _stream(stream)),
+           "ubf_gmres_start")
+
+
+def gmres_step(solver, stream=None):
+    _check(lib().ubf_gmres_step(solver, _stream(stream)), "ubf_gmres_step")
+
+
+def gmres_poll(solver, nrhs: int, wait: bool = False) -> dict:
+    st = _GmresStatus()
+    res = np.zeros(max(1, int(nrhs)), dtype=np.float64)
+    _check(lib().ubf_gmres_poll(solver, int(bool(wait)), ctypes.byref(st), res.ctypes.data),
+           "ubf_gmres_poll")
+    out = {name: getattr(st, name) for name, _ in _GmresStatus._fields_}
+    out["rel_res"] = res[:nrhs]
+    return out
+
+
+def gmres_finish(solver, stream=None):
+    _check(lib().ubf_gmres_finish(solver, _stream(stream)), "ubf_gmres_finish")
+
+
+def gmres_destroy(solver):
+    if solver:
+        lib().ubf_gmres_destroy(solver)
+
+
 # ----------------------------------------------------------- convenience
 
 class FarField:
@@ -363,3 +423,70 @@ class FarField:
                 self.close()
         except Exception:
             pass
+
+
+class Solver:
+    """Restarted GMRES for (sigma I + Z^F) x = b on a :class:`FarField`.
+
+    The Krylov workspace is a device tensor owned here; every step runs in
+    the library's kernels on ``stream`` (default: torch's current stream).
+    ``solve(b)`` returns ``(x, status)`` for a complex64 CUDA tensor ``b`` of
+    shape [nrhs, sum N_b].
+    """
+
+    def __init__(self, field: FarField, sigma, nrhs=1, restart=30, tol=1e-4,
+                 max_steps=300, stream=None):
+        import torch
+        self.field = field
+        self.nrhs = int(nrhs)
+        self.stream = stream
+        nbytes = gmres_workspace_bytes(field.plan, self.nrhs, restart)
+        if nbytes == 0:
+            raise ValueError("nrhs and restart must be in 1..64")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                     device=field.workspace.device)
+        addr = (self.workspace.data_ptr() + 255) & ~255
+        self.solver = gmres_create(field.plan, self.nrhs, restart, sigma, tol, max_steps,
+                                   addr, nbytes)
+
+    def start(self, b, x):
+        self._io = (b, x)
+        gmres_start(self.solver, b, x, self.stream)
+
+    def step(self):
+        gmres_step(self.solver, self.stream)
+
+    def poll(self, wait=False):
+        return gmres_poll(self.solver, self.nrhs, wait)
+
+    def finish(self):
+        gmres_finish(self.solver, self.stream)
+
+    def solve(self, b, x=None, check_every=1):
+        """Run to convergence (or max_steps); waits for the status every
+        ``check_every`` steps."""
+        import torch
+        x = torch.empty_like(b) if x is None else x
+        self.start(b, x)
+        st = self.poll(wait=True)
+        n = 0
+        while not st["done"]:
+            self.step()
+            n += 1
+            if n % check_every == 0:
+                st = self.poll(wait=True)
+        st = self.poll(wait=True)
+        self.finish()
+        return x, st
+
+    def close(self):
+        gmres_destroy(self.solver)
+        self.solver = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "solver", None):
+                self.close()
+        except Exception:
+            pass
+

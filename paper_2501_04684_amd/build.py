@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libubf.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["plan.cpp", "capi.cpp"]
-HIP_SOURCES = ["kernels.hip"]
+HOST_SOURCES = ["plan.cpp", "capi.cpp", "solver.cpp"]
+HIP_SOURCES = ["kernels.hip", "gmres.hip"]
 
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-Wextra",
               "-Wno-unused-parameter", "-D__HIP_PLATFORM_AMD__",

@@ -7,37 +7,14 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ubf.h"
+#include "capi_internal.hpp"
 #include "kernels.hpp"
-#include "plan.hpp"
 
-struct ubf_plan {
-  ubf::Plan p;
-  // Stage timing (ubf_profile_begin/end): 4 events per recorded call.
-  std::vector<hipEvent_t> events;
-  int32_t prof_max = 0;
-  int32_t prof_n = 0;
-  bool profiling = false;
-  // Captured three-stage product (ubf_plan_capture / ubf_plan_replay).
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cap_stream = nullptr;
-  void drop_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
-  }
-  ~ubf_plan() {
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    drop_graph();
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  }
-};
+namespace ubf {
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
 int fail(int status, const std::string& why) {
   g_last_error = why;
@@ -53,6 +30,37 @@ int hip_fail(int err, const char* what) {
   return fail(UBF_EDEVICE, std::string(what) + ": " +
                                hipGetErrorString((hipError_t)err));
 }
+
+const std::string& last_error_text() { return g_last_error; }
+
+int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStream_t s,
+                hipEvent_t* ev) {
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  int e = launch_aggregate(p, d_x, p.d_P, nrhs, s);
+  if (e) return hip_fail(e, "aggregate launch");
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  e = launch_translate(p, p.d_P, p.d_part, nrhs, s);
+  if (e) return hip_fail(e, "translate launch");
+  if (ev && hipEventRecord(ev[2], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  e = launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, s);
+  if (e) return hip_fail(e, "disaggregate launch");
+  if (ev && hipEventRecord(ev[3], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+  return ok();
+}
+
+}  // namespace ubf
+
+namespace {
+
+using ubf::enqueue_mvm;
+using ubf::fail;
+using ubf::hip_fail;
+using ubf::ok;
+
+
+
+
+
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
@@ -109,21 +117,6 @@ int create(const ubf_problem* problem, const int64_t* scat_ptr, int64_t n_scat,
   return ok();
 }
 
-// The three stages of the product, enqueued on `s` (ev: optional events).
-int enqueue_mvm(const ubf::Plan& p, const void* d_x, void* d_y, int32_t nrhs,
-                hipStream_t s, hipEvent_t* ev) {
-  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  int e = ubf::launch_aggregate(p, d_x, p.d_P, nrhs, s);
-  if (e) return hip_fail(e, "aggregate launch");
-  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  e = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, s);
-  if (e) return hip_fail(e, "translate launch");
-  if (ev && hipEventRecord(ev[2], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  e = ubf::launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, s);
-  if (e) return hip_fail(e, "disaggregate launch");
-  if (ev && hipEventRecord(ev[3], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  return ok();
-}
 
 }  // namespace
 
@@ -264,7 +257,7 @@ int ubf_plan_capture(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs) {
   e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   const int launched = enqueue_mvm(plan->p, d_x, d_y, nrhs, plan->cap_stream, nullptr);
-  const std::string why = g_last_error;
+  const std::string why = ubf::last_error_text();
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(plan->cap_stream, &g);
   if (launched != UBF_OK) {
@@ -343,7 +336,7 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (status != UBF_OK) {
-    why = g_last_error;
+    why = ubf::last_error_text();
     ubf::partition_groups(p, before);
     (void)upload();
     return fail(status, why);
@@ -506,6 +499,6 @@ const char* ubf_status_string(int status) {
   }
 }
 
-const char* ubf_last_error(void) { return g_last_error.c_str(); }
+const char* ubf_last_error(void) { return ubf::last_error_text().c_str(); }
 
 }  // extern "C"

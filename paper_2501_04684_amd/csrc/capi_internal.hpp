@@ -1,0 +1,49 @@
+// Internal declarations shared by the C ABI sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ubf.h"
+#include "plan.hpp"
+
+struct ubf_plan {
+  ubf::Plan p;
+  // Stage timing (ubf_profile_begin/end): 4 events per recorded call.
+  std::vector<hipEvent_t> events;
+  int32_t prof_max = 0;
+  int32_t prof_n = 0;
+  bool profiling = false;
+  // Captured three-stage product (ubf_plan_capture / ubf_plan_replay).
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~ubf_plan() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+namespace ubf {
+
+// Error reporting: set the thread-local message and return the status.
+int fail(int status, const std::string& why);
+int ok();
+int hip_fail(int err, const char* what);
+const std::string& last_error_text();
+
+// The three stages of the product y = T G S x, enqueued on `s`
+// (ev: optional 4 timing events).
+int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStream_t s,
+                hipEvent_t* ev);
+
+}  // namespace ubf

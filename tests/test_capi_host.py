@@ -18,7 +18,7 @@ A, K = 0.25, 2 * np.pi
 def test_library_exports_every_declared_symbol():
     L = U.lib()
     names = U.declared_symbols()
-    assert len(names) == 21
+    assert len(names) == 28
     for name in names:
         assert hasattr(L, name), name
 
@@ -298,5 +298,32 @@ def test_graph_and_tune_need_a_bound_plan():
         assert L.ubf_plan_replay(None, None) == -1
         info = U.plan_info(plan)
         assert info["translate_groups"] % 8 == 0 and info["n_scatterers"] == 1
+    finally:
+        U.plan_destroy(plan)
+
+
+def test_gmres_checks_before_any_device_call():
+    plan = U.plan_create(W.grid_boxes(3, 3, 3), A, K, 2)
+    try:
+        L = U.lib()
+        out = ctypes.c_void_p()
+        fake = 1 << 20  # aligned, never dereferenced: the plan is unbound
+        assert U.gmres_workspace_bytes(plan, 1, 100) > 0
+        assert U.gmres_workspace_bytes(plan, 1, 129) == 0
+        assert U.gmres_workspace_bytes(plan, 0, 10) == 0
+        st = L.ubf_gmres_create(plan, 1, 10, 1.0, 0.0, 1e-4, 10, fake, 1 << 30,
+                                ctypes.byref(out))
+        assert st == -4 and "not bound" in U.last_error() and not out.value
+        for args, msg in [((0, 10), "nrhs"), ((1, 0), "restart"), ((1, 200), "restart")]:
+            st = L.ubf_gmres_create(plan, args[0], args[1], 1.0, 0.0, 1e-4, 10, fake,
+                                    1 << 30, ctypes.byref(out))
+            assert st == -1 and msg in U.last_error()
+        st = L.ubf_gmres_create(plan, 1, 10, 1.0, 0.0, 0.0, 10, fake, 1 << 30,
+                                ctypes.byref(out))
+        assert st == -1 and "tol" in U.last_error()
+        st = L.ubf_gmres_create(plan, 1, 10, 1.0, 0.0, 1e-4, 10, fake + 4, 1 << 30,
+                                ctypes.byref(out))
+        assert st == -1 and "aligned" in U.last_error()
+        assert L.ubf_gmres_step(None, None) == -1
     finally:
         U.plan_destroy(plan)
