@@ -281,6 +281,23 @@ int ubf_gmres_poll(ubf_gmres* solver, int32_t wait, ubf_gmres_status* out,
  * started again before further steps. Errors: as ubf_gmres_step. */
 int ubf_gmres_finish(ubf_gmres* solver, void* hip_stream);
 
+/* Estimate ||Z^F||_2 (the plan's far-zone product) by `iters` (1..100)
+ * rounds of power iteration on Z^H Z, using Z^H u = conj(Z^F conj(u)):
+ * Z^F is complex symmetric by the reciprocity of the dyadic Green's
+ * function (Eq. 5-6), for the identity basis and for T = S^T. The start
+ * vector comes from a counter hash of `seed` on the device. Each round is
+ * two products on the first right-hand-side row plus FP64 norms; *out
+ * (host) receives the square root of the last Rayleigh quotient, which
+ * approaches the norm from below. Uses the solver's Krylov blocks, so a
+ * solve in progress is abandoned (start again afterwards). Waits for the
+ * stream. Errors: UBF_EINVAL, UBF_ESTATE, UBF_EDEVICE. */
+int ubf_gmres_norm_estimate(ubf_gmres* solver, int32_t iters, uint64_t seed,
+                            void* hip_stream, double* out);
+
+/* Replace the shift sigma of the system (takes effect at the next start or
+ * step). Errors: UBF_EINVAL (null). */
+int ubf_gmres_set_shift(ubf_gmres* solver, double sigma_re, double sigma_im);
+
 /* Release the solver (its pinned status block; the workspace stays the
  * caller's). */
 void ubf_gmres_destroy(ubf_gmres* solver);
@@ -305,8 +322,9 @@ int ubf_plan_operator(const ubf_plan* plan, int32_t o, double* out);
 
 /* Measurement support (not part of the method). Record HIP timing events
  * on the call's stream before and after each of the three stages of the
- * next max_calls ubf_far_mvm calls on this plan (calls beyond that are not
- * recorded). Errors: UBF_EINVAL (max_calls < 1), UBF_EDEVICE. */
+ * next max_calls products on this plan, whether issued by ubf_far_mvm or
+ * by a GMRES solver on the plan (products beyond that are not recorded).
+ * Errors: UBF_EINVAL (max_calls < 1), UBF_EDEVICE. */
 int ubf_profile_begin(ubf_plan* plan, int32_t max_calls);
 
 /* Wait for the recorded calls and release their events. stage_ms (3

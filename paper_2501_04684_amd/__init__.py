@@ -25,7 +25,8 @@ __all__ = [
     "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
     "profile_begin", "profile_end", "plan_destroy", "status_string",
     "last_error", "FarField", "gmres_workspace_bytes", "gmres_create", "gmres_start",
-    "gmres_step", "gmres_poll", "gmres_finish", "gmres_destroy", "Solver",
+    "gmres_step", "gmres_poll", "gmres_finish", "gmres_destroy", "gmres_norm_estimate",
+    "gmres_set_shift", "Solver",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +104,9 @@ _SIGS = {
     "ubf_gmres_step": (ctypes.c_int, [_VP, _VP]),
     "ubf_gmres_poll": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(_GmresStatus), _VP]),
     "ubf_gmres_finish": (ctypes.c_int, [_VP, _VP]),
+    "ubf_gmres_norm_estimate": (ctypes.c_int, [_VP, _I32, ctypes.c_uint64, _VP,
+                                               ctypes.POINTER(ctypes.c_double)]),
+    "ubf_gmres_set_shift": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double]),
     "ubf_gmres_destroy": (None, [_VP]),
     "ubf_plan_destroy": (None, [_VP]),
     "ubf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -350,6 +354,19 @@ def gmres_finish(solver, stream=None):
     _check(lib().ubf_gmres_finish(solver, _stream(stream)), "ubf_gmres_finish")
 
 
+def gmres_norm_estimate(solver, iters: int = 3, seed: int = 0, stream=None) -> float:
+    """||Z^F||_2 estimate by power iteration on the device (waits)."""
+    out = ctypes.c_double(0.0)
+    _check(lib().ubf_gmres_norm_estimate(solver, int(iters), int(seed), _stream(stream),
+                                         ctypes.byref(out)), "ubf_gmres_norm_estimate")
+    return out.value
+
+
+def gmres_set_shift(solver, sigma):
+    sigma = complex(sigma)
+    _check(lib().ubf_gmres_set_shift(solver, sigma.real, sigma.imag), "ubf_gmres_set_shift")
+
+
 def gmres_destroy(solver):
     if solver:
         lib().ubf_gmres_destroy(solver)
@@ -385,6 +402,24 @@ class FarField:
                                    self.max_nrhs, _stream(None)), "ubf_plan_bind")
         self.nb_total = self.info["n_boxes"] * self.info["n_u"]
         self._basis = None
+
+    @classmethod
+    def from_plan(cls, plan, max_nrhs=1, device="cuda", stream=None):
+        """Take ownership of an existing plan handle: allocate its workspace
+        (on torch's current stream) and bind it on ``stream``."""
+        import torch
+        self = cls.__new__(cls)
+        self.plan = plan
+        self.info = plan_info(plan)
+        self.max_nrhs = int(max_nrhs)
+        nbytes = workspace_bytes(plan, self.max_nrhs)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._ws_addr = (self.workspace.data_ptr() + 255) & ~255
+        _check(lib().ubf_plan_bind(plan, self._ws_addr, nbytes, self.max_nrhs,
+                                   _stream(stream)), "ubf_plan_bind")
+        self.nb_total = self.info["n_boxes"] * self.info["n_u"]
+        self._basis = None
+        return self
 
     def set_basis(self, nb_ptr=None, S=None, T=None):
         plan_set_basis(self.plan, nb_ptr, S, T)
@@ -448,6 +483,14 @@ class Solver:
         addr = (self.workspace.data_ptr() + 255) & ~255
         self.solver = gmres_create(field.plan, self.nrhs, restart, sigma, tol, max_steps,
                                    addr, nbytes)
+
+    def norm_estimate(self, iters=3, seed=0):
+        """||Z^F||_2 estimate (power iteration on the device); abandons a
+        solve in progress."""
+        return gmres_norm_estimate(self.solver, iters, seed, self.stream)
+
+    def set_shift(self, sigma):
+        gmres_set_shift(self.solver, sigma)
 
     def start(self, b, x):
         self._io = (b, x)

@@ -234,10 +234,8 @@ int ubf_far_mvm(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs,
                       plan ? basis_vec_bytes(plan->p, nrhs) : 0,
                       plan ? basis_vec_bytes(plan->p, nrhs) : 0);
   if (st != UBF_OK) return st;
-  hipEvent_t* ev = nullptr;
-  if (plan->profiling && plan->prof_n < plan->prof_max)
-    ev = &plan->events[4 * (size_t)plan->prof_n++];
-  return enqueue_mvm(plan->p, d_x, d_y, nrhs, (hipStream_t)hip_stream, ev);
+  return enqueue_mvm(plan->p, d_x, d_y, nrhs, (hipStream_t)hip_stream,
+                     plan->next_events());
 }
 
 int ubf_plan_capture(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs) {

@@ -20,6 +20,11 @@ struct ubf_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap_stream = nullptr;
+  // Events for the next recorded product, or NULL when not profiling.
+  hipEvent_t* next_events() {
+    if (!profiling || prof_n >= prof_max) return nullptr;
+    return &events[4 * (size_t)prof_n++];
+  }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);

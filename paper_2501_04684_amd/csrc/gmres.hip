@@ -305,6 +305,43 @@ __global__ __launch_bounds__(kThreads) void zero_kernel(float2* __restrict__ p, 
     p[i] = make_float2(0.f, 0.f);
 }
 
+// v[i] = (u(2i), u(2i+1)), u uniform in [-1, 1) from a 64-bit counter hash
+// (the finaliser of SplitMix64) of (seed, index): a reproducible start
+// vector with no host transfer.
+__device__ inline double hash_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ __launch_bounds__(kThreads) void rand_fill_kernel(float2* __restrict__ v, int64_t n,
+                                                             uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    v[i] = make_float2((float)hash_uniform(seed, 2 * i), (float)hash_uniform(seed, 2 * i + 1));
+}
+
+// dst = conj(src)
+__global__ __launch_bounds__(kThreads) void conj_kernel(float2* __restrict__ dst,
+                                                        const float2* __restrict__ src,
+                                                        int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const float2 v = src[i];
+    dst[i] = make_float2(v.x, -v.y);
+  }
+}
+
+// scale[0] = 1 / sqrt(nrm[0].x)  (0 for a zero vector)
+__global__ void inv_norm_kernel(const double2* __restrict__ nrm, double* __restrict__ scale) {
+  if (threadIdx.x == 0) {
+    const double n2 = nrm[0].x;
+    scale[0] = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+  }
+}
+
 unsigned grid_for(int64_t n) {
   const int64_t b = (n + kThreads - 1) / kThreads;
   return (unsigned)(b < 1 ? 1 : (b > kDotBlocks ? kDotBlocks : b));
@@ -378,6 +415,21 @@ int launch_gmres_combine(const float2* V, int64_t vstride, const GmresState& st,
 
 int launch_gmres_status(const GmresState& st, int R, GmresStatusRow* out, hipStream_t s) {
   hipLaunchKernelGGL(status_kernel, dim3(1), dim3(64), 0, s, st, R, out);
+  return (int)hipGetLastError();
+}
+
+int launch_gmres_rand(float2* v, int64_t n, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(rand_fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, v, n, seed);
+  return (int)hipGetLastError();
+}
+
+int launch_gmres_conj(float2* dst, const float2* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(conj_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, dst, src, n);
+  return (int)hipGetLastError();
+}
+
+int launch_gmres_inv_norm(const double2* nrm, double* scale, hipStream_t s) {
+  hipLaunchKernelGGL(inv_norm_kernel, dim3(1), dim3(64), 0, s, nrm, scale);
   return (int)hipGetLastError();
 }
 

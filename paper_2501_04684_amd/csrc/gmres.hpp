@@ -58,5 +58,8 @@ int launch_gmres_combine(const float2* V, int64_t vstride, const GmresState& st,
                          int64_t n, int R, hipStream_t s);
 int launch_gmres_status(const GmresState& st, int R, GmresStatusRow* out, hipStream_t s);
 int launch_gmres_zero(float2* p, int64_t total, hipStream_t s);
+int launch_gmres_rand(float2* v, int64_t n, uint64_t seed, hipStream_t s);
+int launch_gmres_conj(float2* dst, const float2* src, int64_t n, hipStream_t s);
+int launch_gmres_inv_norm(const double2* nrm, double* scale, hipStream_t s);
 
 }  // namespace ubf

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <numeric>
 #include <unordered_map>
 
@@ -75,6 +76,92 @@ int32_t cheb(int64_t x, int64_t y, int64_t z) {
 }
 
 int64_t floordiv2(int64_t c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
+
+// One offset's operator image in the table layout. FP32: planes re, im of
+// nu rows of kh floats. Split: G is rounded to FP32 first (as in the FP32
+// path), then hi = bf16(G), lo = bf16(G - hi); planes re.hi, re.lo, im.hi,
+// im.lo of nu rows of khb values. Padding columns are zero.
+void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<double>>& G,
+                  char* dst) {
+  operator_fp64(w, P.a, P.k, P.eta, P.n_d, G);
+  if (!P.split()) {
+    const size_t plane = P.plane_floats();
+    float* re = (float*)dst;
+    float* im = re + plane;
+    std::fill(re, re + 2 * plane, 0.0f);
+    for (int u = 0; u < P.nu; ++u)
+      for (int v = 0; v < P.nu; ++v) {
+        re[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].real();
+        im[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].imag();
+      }
+  } else {
+    const size_t plane = (size_t)P.nu * P.khb;
+    uint16_t* base = (uint16_t*)dst;
+    std::fill(base, base + 4 * plane, (uint16_t)0);
+    for (int u = 0; u < P.nu; ++u)
+      for (int v = 0; v < P.nu; ++v) {
+        const std::complex<double> g = G[(size_t)u * P.nu + v];
+        const float parts[2] = {(float)g.real(), (float)g.imag()};
+        for (int c = 0; c < 2; ++c) {
+          const uint16_t hi = bf16_bits(parts[c]);
+          const uint16_t lo = bf16_bits(parts[c] - bf16_value(hi));
+          base[(2 * c) * plane + (size_t)u * P.khb + v] = hi;
+          base[(2 * c + 1) * plane + (size_t)u * P.khb + v] = lo;
+        }
+      }
+  }
+}
+
+// Process-wide cache of operator images for offsets within +-3 (every
+// ILIST offset), keyed by the exact parameters; bounded in bytes. Plans of
+// repeated problems (serving) then skip the FP64 Green's evaluations.
+struct ImageKey {
+  double a, k, eta;
+  int32_t n_d, precision, w0, w1, w2;
+  bool operator==(const ImageKey& o) const {
+    return a == o.a && k == o.k && eta == o.eta && n_d == o.n_d &&
+           precision == o.precision && w0 == o.w0 && w1 == o.w1 && w2 == o.w2;
+  }
+};
+struct ImageKeyHash {
+  size_t operator()(const ImageKey& x) const {
+    uint64_t h = 0;
+    auto mix = [&h](uint64_t v) { h = (h ^ v) * 0x100000001B3ull + 0x9E3779B97F4A7C15ull; };
+    uint64_t bits;
+    std::memcpy(&bits, &x.a, 8); mix(bits);
+    std::memcpy(&bits, &x.k, 8); mix(bits);
+    std::memcpy(&bits, &x.eta, 8); mix(bits);
+    mix((uint32_t)x.n_d); mix((uint32_t)x.precision);
+    mix((uint32_t)x.w0); mix((uint32_t)x.w1); mix((uint32_t)x.w2);
+    return (size_t)h;
+  }
+};
+constexpr size_t kImageCacheBytes = size_t(256) << 20;
+std::mutex g_image_mu;
+std::unordered_map<ImageKey, std::vector<char>, ImageKeyHash> g_images;
+size_t g_image_bytes = 0;
+
+bool cacheable(const int32_t* w) {
+  return std::abs(w[0]) <= 3 && std::abs(w[1]) <= 3 && std::abs(w[2]) <= 3;
+}
+ImageKey image_key(const Plan& P, const int32_t* w) {
+  return ImageKey{P.a, P.k, P.eta, P.n_d, P.precision, w[0], w[1], w[2]};
+}
+bool image_cache_get(const Plan& P, const int32_t* w, char* dst, size_t bytes) {
+  if (!cacheable(w)) return false;
+  std::lock_guard<std::mutex> lock(g_image_mu);
+  auto it = g_images.find(image_key(P, w));
+  if (it == g_images.end() || it->second.size() != bytes) return false;
+  std::memcpy(dst, it->second.data(), bytes);
+  return true;
+}
+void image_cache_put(const Plan& P, const int32_t* w, const char* src, size_t bytes) {
+  if (!cacheable(w)) return;
+  std::lock_guard<std::mutex> lock(g_image_mu);
+  if (g_image_bytes + bytes > kImageCacheBytes) return;
+  auto ins = g_images.emplace(image_key(P, w), std::vector<char>(src, src + bytes));
+  if (ins.second) g_image_bytes += bytes;
+}
 
 }  // namespace
 
@@ -243,10 +330,42 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   }
   if ((int64_t)pj.size() > kMaxPairs) return "far set exceeds 2^31-1 pairs";
 
-  // Distinct offsets, lexicographic.
-  std::vector<std::array<int32_t, 3>> uniq(pw);
-  std::sort(uniq.begin(), uniq.end());
-  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  // Distinct offsets, lexicographic: collect them through a hash of the
+  // pairs' offsets (far fewer than pairs), sort only those, then map.
+  const int64_t np = (int64_t)pj.size();
+  std::vector<int32_t> oid(np);
+  std::vector<std::array<int32_t, 3>> uniq;
+  {
+    struct Hash {
+      size_t operator()(const std::array<int32_t, 3>& w) const {
+        uint64_t h = (uint32_t)w[0];
+        h = h * 0x9E3779B97F4A7C15ull ^ (uint32_t)w[1];
+        h = h * 0x9E3779B97F4A7C15ull ^ (uint32_t)w[2];
+        return (size_t)(h ^ (h >> 29));
+      }
+    };
+    std::unordered_map<std::array<int32_t, 3>, int32_t, Hash> seen;
+    for (int64_t p = 0; p < np; ++p) {
+      auto it = seen.find(pw[p]);
+      if (it == seen.end()) {
+        it = seen.emplace(pw[p], (int32_t)uniq.size()).first;
+        uniq.push_back(pw[p]);
+      }
+      oid[p] = it->second;
+    }
+    std::vector<int32_t> order(uniq.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(),
+              [&](int32_t x, int32_t y) { return uniq[x] < uniq[y]; });
+    std::vector<int32_t> rank(uniq.size());
+    std::vector<std::array<int32_t, 3>> sorted(uniq.size());
+    for (size_t r = 0; r < order.size(); ++r) {
+      rank[order[r]] = (int32_t)r;
+      sorted[r] = uniq[order[r]];
+    }
+    uniq.swap(sorted);
+    for (int64_t p = 0; p < np; ++p) oid[p] = rank[oid[p]];
+  }
   const int64_t n_off = (int64_t)uniq.size();
   const double table_bytes = precision == 1
       ? (double)n_off * 4.0 * P.nu * half_len_bf16(P.nu) * sizeof(uint16_t)
@@ -256,11 +375,7 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   for (int64_t o = 0; o < n_off; ++o)
     for (int d = 0; d < 3; ++d) P.offsets[3 * o + d] = uniq[o][d];
 
-  // Offset index of every pair, then a stable counting sort by offset.
-  const int64_t np = (int64_t)pj.size();
-  std::vector<int32_t> oid(np);
-  for (int64_t p = 0; p < np; ++p)
-    oid[p] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), pw[p]) - uniq.begin());
+  // Stable counting sort of the pairs by offset.
   P.off_ptr.assign(n_off + 1, 0);
   for (int64_t p = 0; p < np; ++p) P.off_ptr[oid[p] + 1]++;
   for (int64_t o = 0; o < n_off; ++o) P.off_ptr[o + 1] += P.off_ptr[o];
@@ -310,40 +425,20 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   std::sort(keys.begin(), keys.end());
   P.n_orbits = (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
 
-  // Operator table image.
+  // Operator table image, one offset at a time (cached across plans).
+  const size_t img_bytes = P.split() ? (size_t)4 * P.nu * P.khb * sizeof(uint16_t)
+                                     : (size_t)2 * P.nu * P.kh * sizeof(float);
+  if (P.split())
+    P.table_bf16.assign((size_t)n_off * img_bytes / sizeof(uint16_t), 0);
+  else
+    P.table.assign((size_t)n_off * img_bytes / sizeof(float), 0.0f);
+  char* table = P.split() ? (char*)P.table_bf16.data() : (char*)P.table.data();
   std::vector<std::complex<double>> G;
-  if (!P.split()) {
-    const size_t plane = P.plane_floats();
-    P.table.assign((size_t)n_off * 2 * plane, 0.0f);
-    for (int64_t o = 0; o < n_off; ++o) {
-      operator_fp64(&P.offsets[3 * o], P.a, P.k, P.eta, n_d, G);
-      float* re = &P.table[(size_t)o * 2 * plane];
-      float* im = re + plane;
-      for (int u = 0; u < P.nu; ++u)
-        for (int v = 0; v < P.nu; ++v) {
-          re[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].real();
-          im[(size_t)u * P.kh + v] = (float)G[(size_t)u * P.nu + v].imag();
-        }
-    }
-  } else {
-    // G (rounded to FP32 first, like the FP32 path) = hi + lo, hi = bf16(G),
-    // lo = bf16(G - hi). Planes per offset: re.hi, re.lo, im.hi, im.lo.
-    const size_t plane = (size_t)P.nu * P.khb;
-    P.table_bf16.assign((size_t)n_off * 4 * plane, 0);
-    for (int64_t o = 0; o < n_off; ++o) {
-      operator_fp64(&P.offsets[3 * o], P.a, P.k, P.eta, n_d, G);
-      uint16_t* base = &P.table_bf16[(size_t)o * 4 * plane];
-      for (int u = 0; u < P.nu; ++u)
-        for (int v = 0; v < P.nu; ++v) {
-          const std::complex<double> g = G[(size_t)u * P.nu + v];
-          const float parts[2] = {(float)g.real(), (float)g.imag()};
-          for (int c = 0; c < 2; ++c) {
-            const uint16_t hi = bf16_bits(parts[c]);
-            const uint16_t lo = bf16_bits(parts[c] - bf16_value(hi));
-            base[(2 * c) * plane + (size_t)u * P.khb + v] = hi;
-            base[(2 * c + 1) * plane + (size_t)u * P.khb + v] = lo;
-          }
-        }
+  for (int64_t o = 0; o < n_off; ++o) {
+    char* dst = table + (size_t)o * img_bytes;
+    if (!image_cache_get(P, &P.offsets[3 * o], dst, img_bytes)) {
+      offset_image(P, &P.offsets[3 * o], G, dst);
+      image_cache_put(P, &P.offsets[3 * o], dst, img_bytes);
     }
   }
   return std::string();

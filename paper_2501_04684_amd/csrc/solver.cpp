@@ -7,6 +7,7 @@
 // step), so steps can be queued back to back without waiting.
 #include <hip/hip_runtime_api.h>
 
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -253,7 +254,7 @@ int ubf_gmres_step(ubf_gmres* s, void* hip_stream) {
   const int R = s->R, j = s->j, ld = s->m + 1;
   const int64_t n = s->n, vs = (int64_t)R * n;
   // w = (sigma I + Z^F) v_j
-  e = ubf::enqueue_mvm(s->plan->p, col(s, j), s->W, R, q, nullptr);
+  e = ubf::enqueue_mvm(s->plan->p, col(s, j), s->W, R, q, s->plan->next_events());
   if (e) return e;
   UBF_TRY(ubf::launch_gmres_add_shift(s->W, col(s, j), s->sr, s->si, vs, q), "shift");
   // two classical Gram-Schmidt passes against v_0..v_j
@@ -272,7 +273,7 @@ int ubf_gmres_step(ubf_gmres* s, void* hip_stream) {
   if (s->j == s->m) {  // restart: x += V y, r = b - A x
     e = close_cycle(s, q);
     if (e) return e;
-    e = ubf::enqueue_mvm(s->plan->p, s->x, s->W, R, q, nullptr);
+    e = ubf::enqueue_mvm(s->plan->p, s->x, s->W, R, q, s->plan->next_events());
     if (e) return e;
     UBF_TRY(ubf::launch_gmres_residual(col(s, 0), s->b, s->x, s->W, s->sr, s->si, vs, q),
             "residual");
@@ -318,6 +319,50 @@ int ubf_gmres_finish(ubf_gmres* s, void* hip_stream) {
   e = close_cycle(s, (hipStream_t)hip_stream);
   if (e) return e;
   s->finished = true;
+  return ok();
+}
+
+int ubf_gmres_norm_estimate(ubf_gmres* s, int32_t iters, uint64_t seed, void* hip_stream,
+                            double* out) {
+  int e = check_solver(s);
+  if (e) return e;
+  if (!out) return fail(UBF_EINVAL, "out is NULL");
+  if (iters < 1 || iters > 100) return fail(UBF_EINVAL, "iters must be in 1..100");
+  hipStream_t q = (hipStream_t)hip_stream;
+  const int64_t n = s->n;
+  float2* v = col(s, 0);  // first right-hand-side row of two Krylov blocks
+  float2* u = col(s, 1);
+  s->started = false;     // the Krylov blocks are overwritten
+  UBF_TRY(ubf::launch_gmres_rand(v, n, seed, q), "rand");
+  UBF_TRY(ubf::launch_gmres_dots(v, 0, 1, v, n, 1, s->partial, s->st.nrm, 1, q), "norm");
+  UBF_TRY(ubf::launch_gmres_inv_norm(s->st.nrm, s->st.scale, q), "inv norm");
+  UBF_TRY(ubf::launch_gmres_scale(v, v, s->st.scale, n, 1, q), "scale");
+  for (int it = 0; it < iters; ++it) {
+    // u = conj(Z conj(Z v)) = Z^H Z v  (Z complex symmetric)
+    e = ubf::enqueue_mvm(s->plan->p, v, s->W, 1, q, nullptr);
+    if (e) return e;
+    UBF_TRY(ubf::launch_gmres_conj(u, s->W, n, q), "conj");
+    e = ubf::enqueue_mvm(s->plan->p, u, s->W, 1, q, nullptr);
+    if (e) return e;
+    UBF_TRY(ubf::launch_gmres_conj(u, s->W, n, q), "conj");
+    // Rayleigh quotient v^H u (||v|| = 1), then v = u / ||u||
+    UBF_TRY(ubf::launch_gmres_dots(v, 0, 1, u, n, 1, s->partial, s->st.h1, 1, q), "dots");
+    UBF_TRY(ubf::launch_gmres_dots(u, 0, 1, u, n, 1, s->partial, s->st.nrm, 1, q), "norm");
+    UBF_TRY(ubf::launch_gmres_inv_norm(s->st.nrm, s->st.scale, q), "inv norm");
+    UBF_TRY(ubf::launch_gmres_scale(v, u, s->st.scale, n, 1, q), "scale");
+  }
+  double2 rq;
+  hipError_t he = hipMemcpyAsync(&rq, s->st.h1, sizeof(rq), hipMemcpyDeviceToHost, q);
+  if (he == hipSuccess) he = hipStreamSynchronize(q);
+  if (he != hipSuccess) return hip_fail(he, "norm estimate readback");
+  *out = std::sqrt(std::sqrt(rq.x * rq.x + rq.y * rq.y));
+  return ok();
+}
+
+int ubf_gmres_set_shift(ubf_gmres* s, double sigma_re, double sigma_im) {
+  if (!s) return fail(UBF_EINVAL, "solver is NULL");
+  s->sr = sigma_re;
+  s->si = sigma_im;
   return ok();
 }
 

@@ -26,6 +26,7 @@ __all__ = [
     "mask_boxes",
     "hollow_cube_boxes",
     "scatterer_set",
+    "serving_requests",
     "complex_normal",
     "random_basis",
     "config",
@@ -127,6 +128,30 @@ def scatterer_set(count: int, seed: int, lo: int = 200, hi: int = 20000,
     return out
 
 
+def serving_requests(count: int, rate: float, seed: int, lo: int = 500,
+                     hi: int = 50000, max_nrhs: int = 8) -> list[dict]:
+    """A Poisson stream of solve requests on random-occupancy grids.
+
+    Inter-arrival times are exponential with mean ``1/rate`` seconds; box
+    counts are log-uniform in ``[lo, hi]`` on Bernoulli(rho) masks with rho
+    uniform in [0.1, 1.0]; 1..``max_nrhs`` right-hand sides (uniform).
+    Returns dicts with ``arrival``, ``boxes``, ``nrhs`` and ``b_seed`` (the
+    seed of the request's right-hand sides, see ``complex_normal``).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        target = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+        rho = float(rng.uniform(0.1, 1.0))
+        boxes = mask_boxes(target, rho, int(rng.integers(1 << 31)))
+        out.append({"arrival": t, "boxes": boxes,
+                    "nrhs": int(rng.integers(1, max_nrhs + 1)),
+                    "b_seed": int(rng.integers(1 << 31))})
+    return out
+
+
 def complex_normal(shape, seed: int, dtype=np.complex64) -> np.ndarray:
     """i.i.d. N(0,1) real and imaginary parts."""
     rng = np.random.default_rng(seed)
@@ -195,6 +220,9 @@ def config(idx: int, **over) -> Workload:
        a = 0.25, four right-hand sides each; ``boxes`` is their
        concatenation and ``extra["scatterers"]`` the list of box arrays
        (``count=`` picks another number of scatterers).
+
+    The serving stream (Poisson arrivals of solves on random-occupancy
+    grids) is ``serving_requests``.
     """
     if idx == 1:
         w = Workload("grid6_a0.25", grid_boxes(6, 6, 6), 0.25, TWO_PI, 3,
