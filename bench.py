@@ -9,10 +9,12 @@ basis functions per box), as an iterative solver would issue it. Inputs
 (50 seeded vectors, cycled) and the basis matrices are resident in HBM
 before timing starts; the plan (far set, operator table) is built once.
 
-The headline form is the split-precision translation (BF16 hi/lo operands,
-three products, FP32 accumulation), which stays within the 1e-4 relative
-error of the plain FP32 form; the plain FP32 form is timed after it and
-reported under "compare" with the speedup.
+The headline form is the split-precision translation in FP16 (operands as
+FP16 hi/lo pairs with power-of-two scales, three products, FP32
+accumulation), whose error against the FP64 oracle is that of the plain
+FP32 form; the plain FP32 form is timed after it and reported under
+"compare" with the speedup. ``--precision`` selects split-bf16, fp16 (one
+FP16 product, about 3e-4) or fp32 instead.
 
 ``--workload 5`` runs the serving workload: a Poisson stream of GMRES
 solves (tolerance 1e-4) on random-occupancy grids of 500 to 50k boxes with
@@ -47,6 +49,20 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E peak
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_04684_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_mvm_shell3338_hbm_traffic.json")
+# Stage-2 forms: (dtype label, BF16/FP16 products per pair or 0 for FP32)
+FORMS = {"split-bf16": ("f32 (stage 2 bf16 hi/lo x3, f32 accumulation)", 3),
+         "split-fp16": ("f32 (stage 2 fp16 hi/lo x3, scaled, f32 accumulation)", 3),
+         "fp16": ("f32 (stage 2 fp16 x1, scaled, f32 accumulation)", 1),
+         "fp32": ("f32", 0)}
+
+
+def issued_16bit_flops(form, nu, n_pairs, nrhs):
+    """MFMA flops a 16-bit form issues: products x 2 x (rows padded to 32-row
+    blocks) x (K = 2 halves padded to 8) per pair and RHS."""
+    khb = (nu + 7) // 8 * 8
+    return FORMS[form][1] * 2 * (-(-2 * nu // 32) * 32) * (2 * khb) * n_pairs * nrhs
+
+
 STAGE_KERNELS = {"aggregate": "aggregate_kernel",
                  "translate_mfma": "translate_mfma_kernel",
                  "translate_split": "translate_split_kernel",
@@ -119,7 +135,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["split-bf16", "fp32"], default="split-bf16",
+    ap.add_argument("--precision", choices=list(FORMS), default="split-fp16",
                     help="form timed for the headline value (the other form is "
                          "timed after it for comparison unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
@@ -330,10 +346,9 @@ def bench_batch(args, U, W, torch):
                            warmup, steps)
     info, avg_us = res["info"], res["avg_us"]
     n_pairs, n_box, nu, nrhs = info["n_pairs"], info["n_boxes"], info["n_u"], w.nrhs
-    split = chosen == "split-bf16"
+    split = FORMS[chosen][1] > 0
     flops = info["translate_flops"] * nrhs
-    khb = (nu + 7) // 8 * 8
-    issued = 3 * 2 * (-(-2 * nu // 32) * 32) * (2 * khb) * n_pairs * nrhs
+    issued = issued_16bit_flops(chosen, nu, n_pairs, nrhs) if split else flops
     ach = (issued if split else flops) / (avg_us[1] * 1e-6) / 1e12
     peak = PEAK_BF16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
     box_bytes = nrhs * n_box * nu * 8
@@ -349,7 +364,7 @@ def bench_batch(args, U, W, torch):
         "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": res["dt"] / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 (stage 2 bf16 hi/lo x3, f32 accumulation)" if split else "f32",
+        "dtype": FORMS[chosen][0],
         "data": "synthetic",
         "config": {"workload": w.name, "scatterers": len(kinds),
                    "kinds": {k: kinds.count(k) for k in sorted(set(kinds))},
@@ -414,7 +429,7 @@ def bench_serve(args, U, W, torch):
     area = sum((t1 - t0) * n for (t0, n, _), (t1, _, _) in zip(log, log[1:]))
     conc = area / max(log[-1][0] - log[0][0], 1e-9) if len(log) > 1 else 0.0
     # dominant kernel: stage-2 launches of every product, HIP events per stage
-    split = args.precision == "split-bf16"
+    split = FORMS[args.precision][1] > 0
     flops = issued = t_tr = t_all = 0.0
     nu = 81
     khb = (nu + 7) // 8 * 8
@@ -423,7 +438,8 @@ def bench_serve(args, U, W, torch):
             continue
         per = r.products_timed * r.nrhs
         flops += r.translate_flops * per
-        issued += 3 * 2 * (-(-2 * nu // 32) * 32) * (2 * khb) * r.n_pairs * per
+        issued += (issued_16bit_flops(args.precision, nu, r.n_pairs, per) if split
+                   else r.translate_flops * per)
         t_tr += r.stage_ms[1] * 1e-3
         t_all += r.stage_ms.sum() * 1e-3
     ach = (issued if split else flops) / t_tr / 1e12
@@ -432,7 +448,7 @@ def bench_serve(args, U, W, torch):
         "metric": "far-zone MVMs/s", "value": mvms / wall, "unit": "MVM/s", "n_gpus": 1,
         "steps": len(ok), "warmup": 1, "ms_per_step": wall / max(len(ok), 1) * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 (stage 2 bf16 hi/lo x3, f32 accumulation)" if split else "f32",
+        "dtype": FORMS[args.precision][0],
         "data": "synthetic",
         "config": {"workload": f"serving_poisson{args.rate:g}_masks500-50k",
                    "requests": len(reqs), "offered_rate_per_s": args.rate,
@@ -524,7 +540,7 @@ def main():
     n_pairs, n_box, nu = info["n_pairs"], info["n_boxes"], info["n_u"]
     s_bytes = 0 if S is None else S.nbytes
     stage_names = ["aggregate", "translate", "disaggregate"]
-    split = chosen == "split-bf16"
+    split = FORMS[chosen][1] > 0
     translate_kernel = "translate_split" if split else "translate_mfma"
     # algorithmic work per launch
     flops = info["translate_flops"] * nrhs
@@ -533,7 +549,7 @@ def main():
     trans_tflops = flops / (avg_us[1] * 1e-6) / 1e12
     # split form: three BF16 products over 32-row blocks and 8-wide k-steps
     khb = (nu + 7) // 8 * 8
-    issued = 3 * 2 * (-(-2 * nu // 32) * 32) * (2 * khb) * n_pairs * nrhs
+    issued = issued_16bit_flops(chosen, nu, n_pairs, nrhs) if split else flops
     dom = int(np.argmax(avg_us))
     if dom == 1:
         peak = PEAK_BF16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
@@ -567,7 +583,7 @@ def main():
         "n_gpus": 1, "steps": K, "warmup": args.warmup,
         "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (stage 2 bf16 hi/lo x3, f32 accumulation)" if split else "f32",
+        "dtype": FORMS[chosen][0],
         "data": "synthetic",
         "config": {"workload": w.name, "n_boxes": n_box, "n_pairs": n_pairs,
                    "n_offsets": info["n_offsets"], "n_u": nu, "far_mode": w.far_mode,

@@ -71,12 +71,20 @@ enum ubf_far_mode {
 };
 
 enum ubf_precision {
-  UBF_FP32 = 0,       /* FP32 operands, FP32 accumulation */
-  UBF_SPLIT_BF16 = 1  /* stage 2 with operators and coefficients each split
-                         into a BF16 high part and a BF16 remainder,
-                         G P ~ Gh Ph + Gh Pl + Gl Ph on the BF16 matrix cores
-                         with FP32 accumulation (stages 1 and 3 stay FP32);
-                         n_d 1..3 */
+  UBF_FP32 = 0,        /* FP32 operands, FP32 accumulation */
+  UBF_SPLIT_BF16 = 1,  /* stage 2 with operators and coefficients each split
+                          into a BF16 high part and a BF16 remainder,
+                          G P ~ Gh Ph + Gh Pl + Gl Ph on the BF16 matrix cores
+                          with FP32 accumulation (stages 1 and 3 stay FP32);
+                          n_d 1..3 */
+  UBF_SPLIT_FP16 = 2,  /* as UBF_SPLIT_BF16 with FP16 parts: each operator is
+                          stored divided by a power of two (per offset) and
+                          each box vector by a power of two (per box and
+                          RHS) so both fit the FP16 range; the scales are
+                          multiplied back into the FP32 result (exact) */
+  UBF_FP16 = 3         /* one FP16 product Gh Ph per pair (scaled as in
+                          UBF_SPLIT_FP16): about 2^-11 relative error per
+                          product, for tolerances near 1e-3 */
 };
 
 /* Problem statement (Sec. 2: box grid, dipoles per box, wavenumber). */
@@ -117,7 +125,7 @@ typedef struct ubf_plan ubf_plan;
  * from FP64 evaluations of Eq. (5)-(6) and (13).
  * Errors: UBF_EINVAL for a null pointer, n_boxes < 1, a negative or
  * duplicate coordinate, a <= 0, k <= 0, eta < 0, n_d outside 1..4 (1..3
- * for UBF_SPLIT_BF16), an unknown far_mode or precision, or a far set
+ * for the 16-bit forms), an unknown far_mode or precision, or a far set
  * beyond 2^31-1 pairs;
  * UBF_ENOMEM if host memory runs out. *out is set only on success. */
 int ubf_plan_create(const ubf_problem* problem, ubf_plan** out);

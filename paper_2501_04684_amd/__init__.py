@@ -18,7 +18,8 @@ import re
 import numpy as np
 
 __all__ = [
-    "UbfError", "FAR_ILIST", "FAR_FULL", "FP32", "SPLIT_BF16", "lib", "library_path",
+    "UbfError", "FAR_ILIST", "FAR_FULL", "FP32", "SPLIT_BF16", "SPLIT_FP16", "FP16", "lib",
+    "library_path",
     "declared_symbols", "plan_create", "plan_create_batch", "workspace_bytes",
     "plan_bind", "plan_capture", "plan_replay", "plan_tune",
     "plan_set_basis", "far_mvm", "aggregate", "translate", "disaggregate",
@@ -35,9 +36,10 @@ HEADER = os.path.join(ROOT, "include", "ubf.h")
 library_path = os.path.join(HERE, "libubf.so")
 
 FAR_ILIST, FAR_FULL = 0, 1
-FP32, SPLIT_BF16 = 0, 1
-_PRECISIONS = {"fp32": FP32, "split-bf16": SPLIT_BF16, FP32: FP32,
-               SPLIT_BF16: SPLIT_BF16}
+FP32, SPLIT_BF16, SPLIT_FP16, FP16 = 0, 1, 2, 3
+_PRECISIONS = {"fp32": FP32, "split-bf16": SPLIT_BF16, "split-fp16": SPLIT_FP16,
+               "fp16": FP16, FP32: FP32, SPLIT_BF16: SPLIT_BF16, SPLIT_FP16: SPLIT_FP16,
+               FP16: FP16}
 _MODES = {"ilist": FAR_ILIST, "full": FAR_FULL, FAR_ILIST: FAR_ILIST,
           FAR_FULL: FAR_FULL}
 

@@ -172,6 +172,7 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
       {L.pair_dst, p.pair_dst.data(), p.pair_dst.size() * sizeof(int32_t)},
       {L.test_ptr, p.test_ptr.data(), p.test_ptr.size() * sizeof(int32_t)},
       {L.nb_ptr, nb.data(), nb.size() * sizeof(int64_t)},
+      {L.off_scale, p.off_scale.data(), p.off_scale.size() * sizeof(float)},
   };
   for (const Copy& c : copies) {
     if (c.n == 0) continue;
@@ -192,6 +193,8 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
   p.d_nb_ptr = (int64_t*)(ws + L.nb_ptr);
   p.d_P = (float*)(ws + L.P);
   p.d_part = (float*)(ws + L.part);
+  p.d_off_scale = (float*)(ws + L.off_scale);
+  p.d_box_scale = (float*)(ws + L.box_scale);
   return ok();
 }
 

@@ -4,6 +4,7 @@
 // and padded in the workspace: [re(N_u), 0.. | im(N_u), 0..], 2*kh floats
 // per box (kh = N_u + 1 rounded up to even), which is also the K-axis
 // layout the matrix-core translation consumes.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -15,6 +16,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
 
 // Round-to-nearest-even FP32 -> BF16 bits (finite inputs), and back.
@@ -25,23 +27,45 @@ __device__ inline unsigned bf16_rne(float f) {
 }
 __device__ inline float bf16_f(unsigned b) { return __uint_as_float(b << 16); }
 
+// Round-to-nearest FP32 -> FP16 bits, and back.
+__device__ inline unsigned short f16_rn(float f) { return __half_as_ushort(__float2half_rn(f)); }
+__device__ inline float f16_f(unsigned short b) { return __half2float(__ushort_as_half(b)); }
+
 // Writes one box-vector coefficient (re, im) at index u of a box vector
-// starting at Pb: FP32 layout [re(kh) | im(kh)] or split layout
-// [re.hi | re.lo | im.hi | im.lo] of khb BF16 values each (hi = bf16(v),
-// lo = bf16(v - hi)).
+// starting at Pb. mode 0: FP32 layout [re(kh) | im(kh)]. Otherwise the
+// 16-bit layout [re.hi | re.lo | im.hi | im.lo] of khb values each, with
+// hi = round(v), lo = round(v - hi): mode 1 in BF16; mode 2 in FP16 of
+// v * inv_scale (the box vector's power-of-two scale).
 __device__ inline void put_coef(float* Pb, int u, float re, float im, int kh, int khb,
-                                bool split) {
-  if (!split) {
+                                int mode, float inv_scale = 1.f) {
+  if (mode == 0) {
     Pb[u] = re;
     Pb[kh + u] = im;
     return;
   }
   unsigned short* q = reinterpret_cast<unsigned short*>(Pb);
-  const unsigned rh = bf16_rne(re), ih = bf16_rne(im);
-  q[u] = (unsigned short)rh;
-  q[khb + u] = (unsigned short)bf16_rne(re - bf16_f(rh));
-  q[2 * khb + u] = (unsigned short)ih;
-  q[3 * khb + u] = (unsigned short)bf16_rne(im - bf16_f(ih));
+  if (mode == 1) {
+    const unsigned rh = bf16_rne(re), ih = bf16_rne(im);
+    q[u] = (unsigned short)rh;
+    q[khb + u] = (unsigned short)bf16_rne(re - bf16_f(rh));
+    q[2 * khb + u] = (unsigned short)ih;
+    q[3 * khb + u] = (unsigned short)bf16_rne(im - bf16_f(ih));
+    return;
+  }
+  re *= inv_scale;  // exact: a power of two
+  im *= inv_scale;
+  const unsigned short rh = f16_rn(re), ih = f16_rn(im);
+  q[u] = rh;
+  q[khb + u] = f16_rn(re - f16_f(rh));
+  q[2 * khb + u] = ih;
+  q[3 * khb + u] = f16_rn(im - f16_f(ih));
+}
+
+// Power-of-two scale bringing a box vector's largest |Re|, |Im| to
+// [2^14, 2^15) (1 for a zero vector); its inverse is exact.
+__device__ inline float box_scale_for(float maxabs) {
+  if (!(maxabs > 0.f)) return 1.f;
+  return ldexpf(1.f, ilogbf(maxabs) - 14);
 }
 
 constexpr int kBlock = 256;
@@ -65,35 +89,59 @@ __device__ inline int xcd_chunk(int bid, int grid) {
 
 __global__ __launch_bounds__(kBlock) void pack_kernel(
     const float2* __restrict__ x, float* __restrict__ P, int64_t n_rows,
-    int nu, int kh, int khb, int split) {
-  const int len = split ? khb : kh;            // coefficients incl. zero pad
-  const int vs = split ? 2 * khb : 2 * kh;     // box vector stride (floats)
+    int nu, int kh, int khb, int mode) {
+  const int len = mode ? khb : kh;             // coefficients incl. zero pad
+  const int vs = mode ? 2 * khb : 2 * kh;      // box vector stride (floats)
   const int64_t total = n_rows * len;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int u = (int)(t % len);
     const int64_t row = t / len;
     const float2 v = u < nu ? x[row * nu + u] : make_float2(0.f, 0.f);
-    put_coef(P + row * vs, u, v.x, v.y, kh, khb, split != 0);
+    put_coef(P + row * vs, u, v.x, v.y, kh, khb, mode);
   }
+}
+
+// FP16 forms: one wavefront per box vector (row); its scale needs the
+// vector's largest component first. nu <= 128.
+__global__ __launch_bounds__(64) void pack_f16_kernel(
+    const float2* __restrict__ x, float* __restrict__ P, float* __restrict__ box_scale,
+    int nu, int khb) {
+  const int64_t row = blockIdx.x;
+  const int l = threadIdx.x;
+  const float2 v0 = l < nu ? x[row * nu + l] : make_float2(0.f, 0.f);
+  const float2 v1 = l + 64 < nu ? x[row * nu + l + 64] : make_float2(0.f, 0.f);
+  float m = fmaxf(fmaxf(fabsf(v0.x), fabsf(v0.y)), fmaxf(fabsf(v1.x), fabsf(v1.y)));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  const float sc = box_scale_for(m);
+  const float inv = 1.f / sc;
+  float* Pb = P + row * 2 * khb;
+  if (l < khb) put_coef(Pb, l, v0.x, v0.y, 0, khb, 2, inv);
+  if (l + 64 < khb) put_coef(Pb, l + 64, v1.x, v1.y, 0, khb, 2, inv);
+  if (l == 0) box_scale[row] = sc;
 }
 
 __global__ __launch_bounds__(kBlock) void unpack_kernel(
     const float* __restrict__ P, float2* __restrict__ out, int64_t n_rows,
-    int nu, int kh, int khb, int split) {
-  const int vs = split ? 2 * khb : 2 * kh;
+    int nu, int kh, int khb, int mode, const float* __restrict__ box_scale) {
+  const int vs = mode ? 2 * khb : 2 * kh;
   const int64_t total = n_rows * nu;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int u = (int)(t % nu);
     const int64_t row = t / nu;
     const float* Pb = P + row * vs;
-    if (!split) {
+    const unsigned short* q = reinterpret_cast<const unsigned short*>(Pb);
+    if (mode == 0) {
       out[t] = make_float2(Pb[u], Pb[kh + u]);
-    } else {
-      const unsigned short* q = reinterpret_cast<const unsigned short*>(Pb);
+    } else if (mode == 1) {
       out[t] = make_float2(bf16_f(q[u]) + bf16_f(q[khb + u]),
                            bf16_f(q[2 * khb + u]) + bf16_f(q[3 * khb + u]));
+    } else {
+      const float sc = box_scale[row];
+      out[t] = make_float2((f16_f(q[u]) + f16_f(q[khb + u])) * sc,
+                           (f16_f(q[2 * khb + u]) + f16_f(q[3 * khb + u])) * sc);
     }
   }
 }
@@ -107,8 +155,9 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(
 __global__ __launch_bounds__(kBlock) void aggregate_kernel(
     const float2* __restrict__ x, const int64_t* __restrict__ nb_ptr,
     const float2* __restrict__ S, float* __restrict__ P, int64_t n_box,
-    int64_t nb_total, int nu, int kh, int khb, int split) {
+    int64_t nb_total, int nu, int kh, int khb, int mode, float* __restrict__ box_scale) {
   __shared__ float2 red[kBlock];
+  __shared__ float wmax[kBlock / 64];
   const int64_t i = blockIdx.x;
   const int r = blockIdx.y;
   const int t = threadIdx.x;
@@ -132,17 +181,27 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(
   }
   red[t] = make_float2(ar, ai);
   __syncthreads();
-  float* Pb = P + ((int64_t)r * n_box + i) * (split ? 2 * khb : 2 * kh);
-  const int len = split ? khb : kh;
-  for (int v = t; v < len; v += kBlock) {
-    float sr = 0.f, si = 0.f;
-    if (v < nu)
-      for (int gg = 0; gg < G; ++gg) {
-        sr += red[gg * nu + v].x;
-        si += red[gg * nu + v].y;
-      }
-    put_coef(Pb, v, sr, si, kh, khb, split != 0);
+  float* Pb = P + ((int64_t)r * n_box + i) * (mode ? 2 * khb : 2 * kh);
+  const int len = mode ? khb : kh;  // <= kBlock: one coefficient per thread
+  float sr = 0.f, si = 0.f;
+  if (t < nu)
+    for (int gg = 0; gg < G; ++gg) {
+      sr += red[gg * nu + t].x;
+      si += red[gg * nu + t].y;
+    }
+  float inv = 1.f;
+  if (mode == 2) {  // FP16: the box vector's scale from its largest component
+    float m = fmaxf(fabsf(sr), fabsf(si));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((t & 63) == 0) wmax[t >> 6] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    const float sc = box_scale_for(m);
+    inv = 1.f / sc;
+    if (t == 0) box_scale[(int64_t)r * n_box + i] = sc;
   }
+  if (t < len) put_coef(Pb, t, sr, si, kh, khb, mode, inv);
 }
 
 // ---------------------------------------------------------------- stage 2
@@ -367,23 +426,46 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
   }
 }
 
-// Split-precision translation on the BF16 matrix cores
-// (v_mfma_f32_32x32x16_bf16, FP32 accumulation). With G = Gh + Gl and
-// P = Ph + Pl (h = bf16 of the value, l = bf16 of the remainder), the
-// product is taken as Gh Ph + Gh Pl + Gl Ph; the dropped Gl Pl term and the
-// representation error of each split are about 2^-16 relative. Work
-// layout, pipelining and stores are those of translate_mfma_kernel: lane l
-// owns column l % 32 and K half h = l / 32; a k-step covers 8 consecutive
-// values of each half (KHB = NU rounded up to 8, zero padded), read as one
-// 16-byte value per lane; the operator's four BF16 planes (re.hi, re.lo,
-// im.hi, im.lo) sit in LDS and -Gi is a sign flip. 32-row blocks cover
-// all 2*NU rows (padding rows read row 0 and are not stored).
-template <int NU>
+template <bool F16>
+struct Mfma16;
+template <>
+struct Mfma16<false> {
+  typedef bf16x8 vec;
+  static __device__ inline floatx16 run(vec a, vec b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16<true> {
+  typedef halfx8 vec;
+  static __device__ inline floatx16 run(vec a, vec b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Split-precision translation on the 16-bit matrix cores
+// (v_mfma_f32_32x32x16_bf16 / _f16, FP32 accumulation). With G = Gh + Gl
+// and P = Ph + Pl (h = the value rounded to 16 bits, l = the remainder
+// rounded), NPROD = 3 takes the product as Gh Ph + Gh Pl + Gl Ph (the
+// dropped Gl Pl term and each split's representation error are about
+// 2^-16 relative in BF16, 2^-22 in FP16); NPROD = 1 takes Gh Ph alone
+// (about 2^-11 in FP16). In FP16 the operator is stored divided by a
+// power of two per offset and each box vector by a power of two per box
+// and RHS; a column's FP32 result is multiplied back by both (exact).
+// Work layout, pipelining and stores are those of translate_mfma_kernel:
+// lane l owns column l % 32 and K half h = l / 32; a k-step covers 8
+// consecutive values of each half (KHB = NU rounded up to 8, zero padded),
+// read as one 16-byte value per lane; the operator's four planes (re.hi,
+// re.lo, im.hi, im.lo) sit in LDS and -Gi is a sign flip. 32-row blocks
+// cover all 2*NU rows (padding rows read row 0 and are not stored).
+template <int NU, bool F16, int NPROD>
 __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const unsigned short* __restrict__ table, const int32_t* __restrict__ chunks,
     const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
     const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
-    float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row) {
+    float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row,
+    const float* __restrict__ off_scale, const float* __restrict__ box_scale) {
+  typedef typename Mfma16<F16>::vec vec16;
   constexpr int KH = (NU + 3) & ~3;      // FP32 half-length (partial rows)
   constexpr int KHB = (NU + 7) & ~7;     // BF16 half-length
   constexpr int PLANE = NU * KHB;        // BF16 values per plane
@@ -432,16 +514,18 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   int src0 = pair_src[i0], dst0 = pair_dst[i0];
   int src1 = pair_src[i1], dst1 = pair_dst[i1];
 
-  bf16x8 bh[NGB], bl[NGB];
+  vec16 bh[NGB], bl[NPROD == 3 ? NGB : 1];
   {
-    const bf16x8* pv = reinterpret_cast<const bf16x8*>(
+    const vec16* pv = reinterpret_cast<const vec16*>(
         P + ((int64_t)rhs * n_box + src0) * VSTR + h * KHB);
 #pragma unroll
     for (int g = 0; g < NGB; ++g) {
       bh[g] = pv[g];
-      bl[g] = pv[NGB + g];
+      if (NPROD == 3) bl[g] = pv[NGB + g];
     }
   }
+  // FP16: the scale of the current chunk's column (this lane's source box)
+  float bsc0 = F16 ? box_scale[(int64_t)rhs * n_box + src0] : 1.f, bsc1 = 1.f;
 
   int staged = -1;
   for (int ch = cbeg; ch < cend; ++ch) {
@@ -464,8 +548,9 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
     const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
     const int64_t i2 = min((int64_t)b2 + col0 + r, last);
-    const bf16x8* pv1 = reinterpret_cast<const bf16x8*>(
+    const vec16* pv1 = reinterpret_cast<const vec16*>(
         P + ((int64_t)rhs * n_box + src1) * VSTR + h * KHB);
+    if (F16) bsc1 = box_scale[(int64_t)rhs * n_box + src1];
     int src2, dst2;
 
     if (col0 < n0) {  // wave-uniform
@@ -474,56 +559,61 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
       for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
 #pragma unroll
       for (int g = 0; g < NGB; ++g) {
-        bf16x8 a_h[RB], a_l[RB];
+        vec16 a_h[RB], a_l[NPROD == 3 ? RB : 1];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           uintx4 ah = *reinterpret_cast<const uintx4*>(lds + abase[rb] + 8 * g);
-          uintx4 al = *reinterpret_cast<const uintx4*>(lds + abase[rb] + PLANE + 8 * g);
           ah ^= asgn[rb];
-          al ^= asgn[rb];
-          a_h[rb] = __builtin_bit_cast(bf16x8, ah);
-          a_l[rb] = __builtin_bit_cast(bf16x8, al);
+          a_h[rb] = __builtin_bit_cast(vec16, ah);
+          if (NPROD == 3) {
+            uintx4 al = *reinterpret_cast<const uintx4*>(lds + abase[rb] + PLANE + 8 * g);
+            al ^= asgn[rb];
+            a_l[rb] = __builtin_bit_cast(vec16, al);
+          }
         }
         // consecutive MFMAs go to different row blocks (independent
-        // accumulators); each block's three products are RB issues apart
+        // accumulators); each block's products are RB issues apart
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h[rb], bh[g], acc[rb], 0, 0, 0);
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_h[rb], bh[g], acc[rb]);
+        if (NPROD == 3) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h[rb], bl[g], acc[rb], 0, 0, 0);
+          for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_h[rb], bl[g], acc[rb]);
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l[rb], bh[g], acc[rb], 0, 0, 0);
+          for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_l[rb], bh[g], acc[rb]);
+        }
         bh[g] = pv1[g];  // next chunk
-        bl[g] = pv1[NGB + g];
+        if (NPROD == 3) bl[g] = pv1[NGB + g];
       }
       src2 = pair_src[i2];
       dst2 = pair_dst[i2];
 
       const int64_t row = (col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
       float* out = part + row * PSTR;
+      const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int r0 = rb * 32 + 8 * q4 + 4 * h;
-          if (rb * 32 + 8 * q4 + 8 <= PSTR)  // same for both halves h
-            *reinterpret_cast<floatx4*>(out + r0) =
-                floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
-                        acc[rb][4 * q4 + 3]};
+          if (rb * 32 + 8 * q4 + 8 <= PSTR) {  // same for both halves h
+            floatx4 v = floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                                acc[rb][4 * q4 + 3]};
+            if (F16) v *= sc;
+            *reinterpret_cast<floatx4*>(out + r0) = v;
+          }
         }
     } else {  // no column of this chunk for this wavefront: fetch the next
 #pragma unroll
       for (int g = 0; g < NGB; ++g) {
         bh[g] = pv1[g];
-        bl[g] = pv1[NGB + g];
+        if (NPROD == 3) bl[g] = pv1[NGB + g];
       }
       src2 = pair_src[i2];
       dst2 = pair_dst[i2];
     }
     o0 = o1; n0 = n1; dst0 = dst1;
     o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;
+    bsc0 = bsc1;
   }
 }
 
@@ -578,8 +668,11 @@ constexpr int kStage = 81 * 81 + 2;
 // E_j into LDS (planar padded, 2*kh floats): either the sum of the box's
 // partial products (its consecutive rows of the partial buffer, read as
 // float4; the row groups' sums are combined through `scratch`) or a
-// complex input vector. Ends with a barrier.
-template <bool FROM_PARTS>
+// complex input vector. Ends with a barrier. With PU > 0 the first PU rows
+// of each row group are all requested before any is used (rows past the
+// box's last one are read clamped and masked out), so they are in flight
+// together with the caller's earlier loads; PU = 0 streams the rows.
+template <bool FROM_PARTS, int PU>
 __device__ inline void gather_E(const float* __restrict__ part,
                                 const int32_t* __restrict__ test_ptr, int64_t n_pairs,
                                 const float2* __restrict__ Ein, int64_t j, int r,
@@ -594,8 +687,23 @@ __device__ inline void gather_E(const float* __restrict__ part,
     const float4* pr = reinterpret_cast<const float4*>(part) + (int64_t)r * n_pairs * R4;
     if (h < H) {
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      int p = p0 + h;
+      if (PU > 0 && p1 > p0) {  // uniform
+        float4 v[PU > 0 ? PU : 1];
+#pragma unroll
+        for (int i = 0; i < PU; ++i) v[i] = pr[(int64_t)min(p + i * H, p1 - 1) * R4 + g];
+#pragma unroll
+        for (int i = 0; i < PU; ++i)
+          if (p + i * H < p1) {
+            acc.x += v[i].x;
+            acc.y += v[i].y;
+            acc.z += v[i].z;
+            acc.w += v[i].w;
+          }
+        p += PU * H;
+      }
 #pragma unroll 4
-      for (int p = p0 + h; p < p1; p += H) {
+      for (; p < p1; p += H) {
         const float4 v = pr[(int64_t)p * R4 + g];
         acc.x += v.x;
         acc.y += v.y;
@@ -692,16 +800,16 @@ __global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
   float2* yb = y + (int64_t)r * nb_total;
 
   if (mode == 0) {
-    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
-                         kh, stage4, Es4);
+    gather_E<FROM_PARTS, 0>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
+                            kh, stage4, Es4);
     for (int u = t; u < nu; u += kBlock) yb[j * nu + u] = make_float2(Es[u], Es[nu + u]);
     return;
   }
   const int64_t start = nb_ptr[j];
   const int64_t nb = nb_ptr[j + 1] - start;
   if (mode == 2) {
-    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
-                         kh, stage4, Es4);
+    gather_E<FROM_PARTS, 0>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
+                            kh, stage4, Es4);
     const float2* Tb = T + start * nu;
     for (int64_t c = t; c < nb; c += kBlock) {
       float sr = 0.f, si = 0.f;
@@ -720,8 +828,8 @@ __global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
   // mode 1
   const int CB = (kStage - 2) / nu;            // columns per batch
   if (nb <= 0) {
-    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
-                         kh, stage4, Es4);
+    gather_E<FROM_PARTS, 0>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu,
+                            kh, stage4, Es4);
     return;
   }
   // First batch: its loads are in flight while E_j is gathered.
@@ -740,7 +848,7 @@ __global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
     for (int it = 0; it < LD; ++it) tmp[it] = s4[min(max(t + it * kBlock, lo), hi)];
     const float2 edge0 = s2[shift ? 1 : 2 * lo];
     const float2 edge1 = s2[(lim & 1) ? 2 * (n4 - 1) : 2 * hi];
-    gather_E<FROM_PARTS>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu, kh, stage4, Es4);
+    gather_E<FROM_PARTS, 8>(part, test_ptr, n_pairs, Ein, j, r, n_box, nu, kh, stage4, Es4);
     floatx4* stagev = reinterpret_cast<floatx4*>(stage4);
 #pragma unroll
     for (int it = 0; it < LD; ++it) {
@@ -818,6 +926,11 @@ bool translate_uses_mfma(const Plan& p) {
 
 int launch_pack(const Plan& p, const void* x, float* P, int nrhs, void* stream) {
   const int64_t rows = (int64_t)nrhs * p.n_box;
+  if (p.fp16()) {
+    hipLaunchKernelGGL(pack_f16_kernel, dim3((unsigned)rows), dim3(64), 0, (hipStream_t)stream,
+                       (const float2*)x, P, p.d_box_scale, p.nu, p.khb);
+    return (int)hipGetLastError();
+  }
   hipLaunchKernelGGL(pack_kernel, dim3(grid_for(rows * (p.split() ? p.khb : p.kh))),
                      dim3(kBlock), 0, (hipStream_t)stream, (const float2*)x, P, rows,
                      p.nu, p.kh, p.khb, p.split() ? 1 : 0);
@@ -828,7 +941,7 @@ int launch_unpack(const Plan& p, const float* P, void* out, int nrhs, void* stre
   const int64_t rows = (int64_t)nrhs * p.n_box;
   hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(rows * p.nu)), dim3(kBlock), 0,
                      (hipStream_t)stream, P, (float2*)out, rows, p.nu, p.kh, p.khb,
-                     p.split() ? 1 : 0);
+                     p.fp16() ? 2 : (p.split() ? 1 : 0), p.d_box_scale);
   return (int)hipGetLastError();
 }
 
@@ -837,7 +950,7 @@ int launch_aggregate(const Plan& p, const void* x, float* P, int nrhs, void* str
   hipLaunchKernelGGL(aggregate_kernel, dim3((unsigned)p.n_box, nrhs), dim3(kBlock), 0,
                      (hipStream_t)stream, (const float2*)x, p.d_nb_ptr,
                      (const float2*)p.d_S, P, p.n_box, p.nb_total(), p.nu, p.kh,
-                     p.khb, p.split() ? 1 : 0);
+                     p.khb, p.fp16() ? 2 : (p.split() ? 1 : 0), p.d_box_scale);
   return (int)hipGetLastError();
 }
 
@@ -850,16 +963,25 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
   const int64_t trash = (int64_t)p.max_nrhs * p.n_pairs();
   if (p.split()) {
     const unsigned short* tb = reinterpret_cast<const unsigned short*>(p.d_table);
-#define UBF_SPLIT(NU)                                                                  \
-  hipLaunchKernelGGL(translate_split_kernel<NU>, groups, dim3(kBlock), 0, s, tb,         \
-                     p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,        \
-                     p.n_box, p.n_pairs(), trash)
-    switch (p.nu) {
-      case 81: UBF_SPLIT(81); break;
-      case 24: UBF_SPLIT(24); break;
-      case 3: UBF_SPLIT(3); break;
-      default: return (int)hipErrorInvalidValue;  // rejected at plan creation
+#define UBF_SPLIT(NU, F16, NPROD)                                                         \
+  hipLaunchKernelGGL((translate_split_kernel<NU, F16, NPROD>), groups, dim3(kBlock), 0, s, \
+                     tb, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,      \
+                     p.n_box, p.n_pairs(), trash, p.d_off_scale, p.d_box_scale)
+#define UBF_SPLIT_NU(F16, NPROD)                           \
+  switch (p.nu) {                                          \
+    case 81: UBF_SPLIT(81, F16, NPROD); break;             \
+    case 24: UBF_SPLIT(24, F16, NPROD); break;             \
+    case 3: UBF_SPLIT(3, F16, NPROD); break;               \
+    default: return (int)hipErrorInvalidValue; /* rejected at plan creation */ \
+  }
+    if (p.precision == 1) {
+      UBF_SPLIT_NU(false, 3);
+    } else if (p.precision == 2) {
+      UBF_SPLIT_NU(true, 3);
+    } else {
+      UBF_SPLIT_NU(true, 1);
     }
+#undef UBF_SPLIT_NU
 #undef UBF_SPLIT
     return (int)hipGetLastError();
   }

@@ -82,8 +82,32 @@ int64_t floordiv2(int64_t c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
 // path), then hi = bf16(G), lo = bf16(G - hi); planes re.hi, re.lo, im.hi,
 // im.lo of nu rows of khb values. Padding columns are zero.
 void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<double>>& G,
-                  char* dst) {
+                  char* dst, float* scale) {
   operator_fp64(w, P.a, P.k, P.eta, P.n_d, G);
+  *scale = 1.0f;
+  if (P.fp16()) {
+    // power of two bringing the largest |Re|, |Im| to [2^14, 2^15)
+    double mx = 0.0;
+    for (const auto& g : G) mx = std::max({mx, std::abs(g.real()), std::abs(g.imag())});
+    const int e = mx > 0.0 ? std::ilogb(mx) - 14 : 0;
+    *scale = (float)std::ldexp(1.0, e);
+    const uint16_t zero = 0;
+    const size_t plane = (size_t)P.nu * P.khb;
+    uint16_t* base = (uint16_t*)dst;
+    std::fill(base, base + 4 * plane, zero);
+    for (int u = 0; u < P.nu; ++u)
+      for (int v = 0; v < P.nu; ++v) {
+        const std::complex<double> g = G[(size_t)u * P.nu + v];
+        const float parts[2] = {(float)std::ldexp(g.real(), -e), (float)std::ldexp(g.imag(), -e)};
+        for (int c = 0; c < 2; ++c) {
+          const uint16_t hi = fp16_bits(parts[c]);
+          const uint16_t lo = fp16_bits(parts[c] - fp16_value(hi));
+          base[(2 * c) * plane + (size_t)u * P.khb + v] = hi;
+          base[(2 * c + 1) * plane + (size_t)u * P.khb + v] = lo;
+        }
+      }
+    return;
+  }
   if (!P.split()) {
     const size_t plane = P.plane_floats();
     float* re = (float*)dst;
@@ -147,19 +171,25 @@ bool cacheable(const int32_t* w) {
 ImageKey image_key(const Plan& P, const int32_t* w) {
   return ImageKey{P.a, P.k, P.eta, P.n_d, P.precision, w[0], w[1], w[2]};
 }
-bool image_cache_get(const Plan& P, const int32_t* w, char* dst, size_t bytes) {
+// An entry holds the image followed by its float scale.
+bool image_cache_get(const Plan& P, const int32_t* w, char* dst, size_t bytes, float* scale) {
   if (!cacheable(w)) return false;
   std::lock_guard<std::mutex> lock(g_image_mu);
   auto it = g_images.find(image_key(P, w));
-  if (it == g_images.end() || it->second.size() != bytes) return false;
+  if (it == g_images.end() || it->second.size() != bytes + sizeof(float)) return false;
   std::memcpy(dst, it->second.data(), bytes);
+  std::memcpy(scale, it->second.data() + bytes, sizeof(float));
   return true;
 }
-void image_cache_put(const Plan& P, const int32_t* w, const char* src, size_t bytes) {
+void image_cache_put(const Plan& P, const int32_t* w, const char* src, size_t bytes,
+                     float scale) {
   if (!cacheable(w)) return;
   std::lock_guard<std::mutex> lock(g_image_mu);
   if (g_image_bytes + bytes > kImageCacheBytes) return;
-  auto ins = g_images.emplace(image_key(P, w), std::vector<char>(src, src + bytes));
+  std::vector<char> entry(src, src + bytes);
+  entry.resize(bytes + sizeof(float));
+  std::memcpy(entry.data() + bytes, &scale, sizeof(float));
+  auto ins = g_images.emplace(image_key(P, w), std::move(entry));
   if (ins.second) g_image_bytes += bytes;
 }
 
@@ -241,6 +271,8 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   L.P = take((size_t)max_nrhs * p.n_box * p.vstride() * sizeof(float));
   // one spare row at the end receives the stores of idle matrix-core lanes
   L.part = take(((size_t)max_nrhs * p.n_pairs() + 1) * p.pstride() * sizeof(float));
+  L.off_scale = take((size_t)std::max<int32_t>(p.n_off(), 1) * sizeof(float));
+  L.box_scale = take((size_t)max_nrhs * p.n_box * sizeof(float));
   L.total = at;
   return L;
 }
@@ -257,8 +289,8 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   if (!(eta >= 0.0) || !std::isfinite(eta)) return "eta must be >= 0 (0 = free space)";
   if (n_d < 1 || n_d > 4) return "n_d must be in 1..4";
   if (far_mode != 0 && far_mode != 1) return "unknown far_mode";
-  if (precision != 0 && precision != 1) return "unknown precision";
-  if (precision == 1 && n_d > 3) return "split precision supports n_d 1..3";
+  if (precision < 0 || precision > 3) return "unknown precision";
+  if (precision >= 1 && n_d > 3) return "split precision supports n_d 1..3";
 
   P.n_box = n_box;
   P.boxes.assign(box_ijk, box_ijk + 3 * n_box);
@@ -434,11 +466,12 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
     P.table.assign((size_t)n_off * img_bytes / sizeof(float), 0.0f);
   char* table = P.split() ? (char*)P.table_bf16.data() : (char*)P.table.data();
   std::vector<std::complex<double>> G;
+  P.off_scale.assign(n_off, 1.0f);
   for (int64_t o = 0; o < n_off; ++o) {
     char* dst = table + (size_t)o * img_bytes;
-    if (!image_cache_get(P, &P.offsets[3 * o], dst, img_bytes)) {
-      offset_image(P, &P.offsets[3 * o], G, dst);
-      image_cache_put(P, &P.offsets[3 * o], dst, img_bytes);
+    if (!image_cache_get(P, &P.offsets[3 * o], dst, img_bytes, &P.off_scale[o])) {
+      offset_image(P, &P.offsets[3 * o], G, dst, &P.off_scale[o]);
+      image_cache_put(P, &P.offsets[3 * o], dst, img_bytes, P.off_scale[o]);
     }
   }
   return std::string();

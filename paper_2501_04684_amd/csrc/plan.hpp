@@ -29,6 +29,46 @@ inline int half_len(int nu) { return (nu + 3) & ~3; }
 // multiple of 8 so a lane's 8 consecutive BF16 values are one 16-byte read.
 inline int half_len_bf16(int nu) { return (nu + 7) & ~7; }
 
+// Round-to-nearest-even FP32 -> FP16 bits (finite inputs within range).
+inline uint16_t fp16_bits(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u;
+  const int32_t e = (int32_t)((x >> 23) & 0xFF) - 127;
+  uint32_t m = x & 0x7FFFFFu;
+  if (e > 15) return (uint16_t)(sign | 0x7C00u);          // overflow -> inf
+  if (e >= -14) {                                          // normal
+    uint32_t h = ((uint32_t)(e + 15) << 10) | (m >> 13);
+    const uint32_t rest = m & 0x1FFFu;
+    if (rest > 0x1000u || (rest == 0x1000u && (h & 1u))) ++h;  // may carry into exp
+    return (uint16_t)(sign | h);
+  }
+  if (e < -25) return (uint16_t)sign;                      // underflow -> 0
+  m |= 0x800000u;                                          // subnormal
+  const int shift = -e - 14 + 13;                          // 14..24
+  uint32_t h = m >> shift;
+  const uint32_t rest = m & ((1u << shift) - 1u), half = 1u << (shift - 1);
+  if (rest > half || (rest == half && (h & 1u))) ++h;
+  return (uint16_t)(sign | h);
+}
+inline float fp16_value(uint16_t b) {
+  const uint32_t sign = (uint32_t)(b & 0x8000u) << 16;
+  const int e = (b >> 10) & 0x1F;
+  const uint32_t m = b & 0x3FFu;
+  float f;
+  if (e == 0) {
+    f = (float)m * 5.9604644775390625e-08f;  // 2^-24
+  } else if (e == 31) {
+    const uint32_t u = sign | 0x7F800000u | (m << 13);
+    std::memcpy(&f, &u, 4);
+    return f;
+  } else {
+    const uint32_t u = ((uint32_t)(e - 15 + 127) << 23) | (m << 13);
+    std::memcpy(&f, &u, 4);
+  }
+  return sign ? -f : f;
+}
+
 // Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
 inline uint16_t bf16_bits(float f) {
   uint32_t u;
@@ -84,9 +124,15 @@ struct Plan {
   // floats; columns >= nu are zero. Split precision instead stores, per
   // offset, planes (re, im) x (hi, lo) of nu rows of khb BF16 values.
   std::vector<float> table;
-  std::vector<uint16_t> table_bf16;
+  std::vector<uint16_t> table_bf16;  // 16-bit image (BF16 or FP16 bits)
+  // FP16 forms: operator o is stored divided by off_scale[o] (a power of
+  // two), so that every operator fits the FP16 range.
+  std::vector<float> off_scale;
   int khb = 0;
-  bool split() const { return precision == 1; }
+  // 16-bit forms (precision 1: BF16 hi/lo; 2: FP16 hi/lo; 3: FP16 single).
+  bool split() const { return precision >= 1; }
+  bool fp16() const { return precision >= 2; }
+  int nprod() const { return precision == 3 ? 1 : 3; }
 
   int64_t n_pairs() const { return (int64_t)pair_src.size(); }
   int32_t n_off() const { return (int32_t)(offsets.size() / 3); }
@@ -117,6 +163,8 @@ struct Plan {
   int64_t* d_nb_ptr = nullptr;
   float* d_P = nullptr;
   float* d_part = nullptr;
+  float* d_off_scale = nullptr;  // [n_off] (FP16 forms)
+  float* d_box_scale = nullptr;  // [max_nrhs][n_box] box-vector scales (FP16 forms)
 
   // Basis.
   bool has_basis = false;
@@ -130,7 +178,8 @@ struct Plan {
 
 // Workspace layout, in bytes from the workspace start.
 struct Layout {
-  size_t table, chunks, wg_ptr, pair_src, pair_dst, test_ptr, nb_ptr, P, part, total;
+  size_t table, chunks, wg_ptr, pair_src, pair_dst, test_ptr, nb_ptr, P, part, off_scale,
+      box_scale, total;
 };
 Layout workspace_layout(const Plan& p, int32_t max_nrhs);
 

@@ -327,3 +327,22 @@ def test_gmres_checks_before_any_device_call():
         assert L.ubf_gmres_step(None, None) == -1
     finally:
         U.plan_destroy(plan)
+
+
+@pytest.mark.parametrize("form,code", [("split-fp16", 2), ("fp16", 3)])
+def test_fp16_plans(form, code):
+    b = W.grid_boxes(4, 4, 4)
+    plan = U.plan_create(b, A, K, 3, "ilist", precision=form)
+    try:
+        info = U.plan_info(plan)
+        assert info["precision"] == code
+        assert info["table_bytes"] == info["n_offsets"] * 4 * 81 * 88 * 2
+    finally:
+        U.plan_destroy(plan)
+    with pytest.raises(U.UbfError):
+        U.plan_create(b, A, K, 4, "ilist", precision=form)
+    bb = np.ascontiguousarray(b.astype(np.int32))
+    prob = U._Problem(len(bb), bb.ctypes.data, A, K, 0.0, 3, 0, 4)
+    out = ctypes.c_void_p()
+    assert U.lib().ubf_plan_create(ctypes.byref(prob), ctypes.byref(out)) == -1
+    assert "precision" in U.last_error()

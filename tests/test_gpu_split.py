@@ -1,10 +1,10 @@
-"""Parity of the split-precision (BF16 hi/lo, three products, FP32
-accumulation) translation with the FP64 oracle (needs a GPU).
+"""Parity of the 16-bit translation forms with the FP64 oracle (needs a GPU).
 
-The paper states no precision; the spec bar for split precision is a
-relative l2 error <= 1e-3. The split of each operand is exact to about
-2^-16 relative, so the expected error is ~1e-5 and the tests assert the
-tighter 1e-4 of the plain FP32 path.
+The paper states no precision; the bar for split precision is a relative
+l2 error <= 1e-3. BF16 hi/lo splits are exact to about 2^-16 relative and
+FP16 hi/lo splits (with power-of-two scaling) to about 2^-22, so both
+three-product forms are held to the 1e-4 of the plain FP32 path. The
+single FP16 product (about 2^-11 per product) is held to 1e-3.
 """
 import numpy as np
 import pytest
@@ -15,6 +15,7 @@ from gpu_util import announce, rel_l2, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
+FORMS = [("split-bf16", 1e-4), ("split-fp16", 1e-4), ("fp16", 1e-3)]
 
 torch = pytest.importorskip("torch")
 U = pytest.importorskip("paper_2501_04684_amd")
@@ -27,16 +28,17 @@ def _need_gpu():
     U.lib()
 
 
-def split_field(w, max_nrhs=1):
+def split_field(w, max_nrhs=1, form="split-bf16"):
     return U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=max_nrhs,
-                      precision="split-bf16")
+                      precision=form)
 
 
+@pytest.mark.parametrize("form,tol", FORMS)
 @pytest.mark.parametrize("cfg", [1, 2])
-def test_split_translate_parity(cfg):
+def test_split_translate_parity(cfg, form, tol):
     w = W.config(cfg)
-    announce("split translate", w.name)
-    ff = split_field(w)
+    announce("split translate", w.name, form)
+    ff = split_field(w, form=form)
     P = w.coefficients().reshape(1, w.n_box, w.n_u)
     Pd = to_dev(P)
     Ed = torch.empty_like(Pd)
@@ -44,16 +46,17 @@ def test_split_translate_parity(cfg):
     E = to_host(Ed)
     ref = O.translate(P.astype(np.complex128), w.boxes, w.a, w.k, w.n_d)
     err = rel_l2(E, ref)
-    print(f"{w.name}: split translate rel_l2 = {err:.3e}")
-    assert err <= TOL
+    print(f"{w.name} {form}: translate rel_l2 = {err:.3e}")
+    assert err <= tol
 
 
-def test_split_three_stage_shell_and_nrhs():
+@pytest.mark.parametrize("form,tol", FORMS)
+def test_split_three_stage_shell_and_nrhs(form, tol):
     w = W.config(2)
-    announce("split three-stage shell nrhs=2", w.name)
+    announce("split three-stage shell nrhs=2", w.name, form)
     nb = np.full(w.n_box, 81)
     nb_ptr, S = W.random_basis(nb, w.n_u, 2)
-    ff = split_field(w, max_nrhs=2)
+    ff = split_field(w, max_nrhs=2, form=form)
     ff.set_basis(nb_ptr, to_dev(S))
     x = W.complex_normal((2, int(nb_ptr[-1])), 3)
     y = to_host(ff(to_dev(x)))
@@ -61,31 +64,56 @@ def test_split_three_stage_shell_and_nrhs():
                     S.astype(np.complex128))
     for r in range(2):
         err = rel_l2(y[r], ref[r])
-        print(f"split three-stage rhs {r}: rel_l2 = {err:.3e}")
-        assert err <= TOL
+        print(f"{form} three-stage rhs {r}: rel_l2 = {err:.3e}")
+        assert err <= tol
 
 
+@pytest.mark.parametrize("form,tol", FORMS)
 @pytest.mark.parametrize("n_d,boxes,a", [
     (1, W.grid_boxes(5, 5, 5), 0.25),
     (2, W.grid_boxes(4, 6, 4), 0.25),
     (3, W.grid_boxes(8, 8, 8), 1.0 / 256),   # low-frequency regime
 ])
-def test_split_other_cases(n_d, boxes, a):
-    announce("split n_d", n_d, "a", a, len(boxes))
-    ff = U.FarField(boxes, a, 2 * np.pi, n_d, "ilist", precision="split-bf16")
+def test_split_other_cases(n_d, boxes, a, form, tol):
+    announce("split n_d", n_d, "a", a, len(boxes), form)
+    ff = U.FarField(boxes, a, 2 * np.pi, n_d, "ilist", precision=form)
     P = W.complex_normal((1, len(boxes), 3 * n_d ** 3), 40 + n_d)
     Pd = to_dev(P)
     Ed = torch.empty_like(Pd)
     U.translate(ff.plan, Pd, Ed, 1)
     ref = O.translate(P.astype(np.complex128), boxes, a, 2 * np.pi, n_d)
-    assert rel_l2(to_host(Ed), ref) <= TOL
+    assert rel_l2(to_host(Ed), ref) <= tol
 
 
-def test_split_deterministic_and_degenerate():
+@pytest.mark.parametrize("form,tol", FORMS)
+def test_split_deterministic_and_degenerate(form, tol):
     w = W.config(1)
-    announce("split determinism", w.name)
-    ff = split_field(w)
+    announce("split determinism", w.name, form)
+    ff = split_field(w, form=form)
     x = to_dev(W.complex_normal((1, w.n_box * w.n_u), 9))
     assert np.array_equal(to_host(ff(x)), to_host(ff(x)))
-    one = U.FarField(np.array([[2, 2, 2]]), 0.25, 2 * np.pi, 3, precision="split-bf16")
+    one = U.FarField(np.array([[2, 2, 2]]), 0.25, 2 * np.pi, 3, precision=form)
     assert not np.any(to_host(one(to_dev(W.complex_normal((1, 81), 1)))))
+
+
+@pytest.mark.parametrize("form,tol", FORMS)
+def test_wide_dynamic_range_across_boxes(form, tol):
+    """Box vectors spanning 10^+-6: the FP16 forms scale each box vector by
+    its own power of two, so the error stays relative per contribution."""
+    w = W.config(1)
+    announce("dynamic range", w.name, form)
+    ff = split_field(w, form=form)
+    P = w.coefficients().reshape(1, w.n_box, w.n_u)
+    mag = 10.0 ** np.random.default_rng(12).uniform(-6, 6, w.n_box)
+    P = (P * mag[None, :, None]).astype(np.complex64)
+    Pd = to_dev(P)
+    Ed = torch.empty_like(Pd)
+    U.translate(ff.plan, Pd, Ed, 1)
+    E = to_host(Ed)
+    ref = O.translate(P.astype(np.complex128), w.boxes, w.a, w.k, w.n_d)
+    # per test box, relative to that box's own field (the sums mix scales)
+    num = np.linalg.norm(E - ref, axis=2)
+    den = np.linalg.norm(ref, axis=2)
+    worst = float((num / den).max())
+    print(f"{form}: worst per-box rel err {worst:.2e}")
+    assert worst <= 30 * tol
