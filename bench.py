@@ -75,7 +75,12 @@ def source_hash(path=KERNEL_SOURCE):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def summarize_pmc(fetch_csv, write_csv, copy_bytes):
+def traffic_key(name, basis, nrhs, far_mode):
+    """The workload a counter summary was taken on."""
+    return f"{name}/{basis}/nrhs{nrhs}/{far_mode}"
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_bytes, workload):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the three stage kernels,
     with the scale factors read off the plain device copy of copy_bytes."""
     import csv
@@ -95,6 +100,7 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes):
     write, write_copy = per_kernel(write_csv, "WRITE_SIZE")
     return {
         "source_sha256": source_hash(),
+        "workload": workload,
         "copy_bytes": copy_bytes,
         "copy_fetch_kib": fetch_copy, "copy_write_kib": write_copy,
         "fetch_scale": copy_bytes / 1024.0 / fetch_copy,
@@ -103,14 +109,15 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes):
     }
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, workload):
     """HBM bytes per launch of `stage` from the committed counter summary,
-    or None when it is missing or the kernel source changed since."""
+    or None when it is missing, was taken on another workload, or the
+    kernel source changed since."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != source_hash():
+    if t.get("source_sha256") != source_hash() or t.get("workload") != workload:
         return None
     f, w = t["fetch_kib"].get(stage), t["write_kib"].get(stage)
     if f is None or w is None:
@@ -130,6 +137,9 @@ def parse():
                     help="serving workload: Poisson arrival rate (requests/s)")
     ap.add_argument("--requests", type=int, default=48,
                     help="serving workload: number of requests")
+    ap.add_argument("--far-mode", choices=["ilist", "full"], default="ilist",
+                    help="far set of workloads 1-3: the interaction list, or every pair "
+                         "with Chebyshev offset >= 2 (FULL)")
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="synthetic workload index (2 = 3,338-box shell)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -186,6 +196,44 @@ def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
         "sample": f"{n} full far-zone MVMs of the same workload in {dt:.1f} s "
                   f"(NumPy FP64, grouped by offset; {len(os.sched_getaffinity(0))} "
                   f"host cores visible, {cpu_model})",
+    }, rel
+
+
+def cpu_baseline_sampled(w, nb_ptr, S, x0, y0_gpu, budget_s, n_pairs, n_sample=4):
+    """FULL far sets (O(N^2) pairs over ~10^5 offsets) are beyond a whole
+    oracle product in the time budget: time the oracle's stage 1 on every
+    box and stages 2-3 on ``n_sample`` test boxes, and scale stage 2 by the
+    far-pair count and stage 3 by the box count."""
+    import numpy as np
+    import oracle as O
+
+    S128 = None if S is None else S.astype(np.complex128)
+    x = x0.astype(np.complex128)
+    rng = np.random.default_rng(17)
+    sample = np.sort(rng.choice(w.n_box, size=n_sample, replace=False))
+    t0 = time.perf_counter()
+    P = O.aggregate(x, nb_ptr, S128, w.n_u) if S128 is not None else x.reshape(1, w.n_box, w.n_u)
+    t1 = time.perf_counter()
+    E = O.translate(P, w.boxes, w.a, w.k, w.n_d, mode=w.far_mode, test_boxes=sample)
+    t2 = time.perf_counter()
+    y = O.disaggregate(E, nb_ptr, S128)
+    t3 = time.perf_counter()
+    j, _, _ = O.far_pairs(w.boxes, w.far_mode)
+    pairs_sample = int(np.isin(j, sample).sum())
+    est = (t1 - t0) + (t2 - t1) * n_pairs / pairs_sample + (t3 - t2)
+    if nb_ptr is None:
+        rows = np.concatenate([np.arange(b * w.n_u, (b + 1) * w.n_u) for b in sample])
+    else:
+        rows = np.concatenate([np.arange(nb_ptr[b], nb_ptr[b + 1]) for b in sample])
+    ref = y[:, rows]
+    rel = float(np.linalg.norm(y0_gpu[:, rows] - ref) / np.linalg.norm(ref))
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": 1.0 / est, "unit": "MVM/s", "cores": cores, "kind": "oracle",
+        "sample": (f"stage 1 on all boxes ({t1 - t0:.1f} s), stages 2-3 on {n_sample} test "
+                   f"boxes ({pairs_sample} far pairs, {t2 - t1:.1f} s), scaled to "
+                   f"{n_pairs} pairs: {est:.0f} s per product (NumPy FP64, {cores} host "
+                   f"cores visible, {cpu_model()})"),
     }, rel
 
 
@@ -506,8 +554,10 @@ def bench_serve(args, U, W, torch):
 def main():
     args = parse()
     if args.summarize_pmc:
+        import workloads as W
+        key = traffic_key(W.config(args.workload).name, args.basis, args.nrhs, args.far_mode)
         print(json.dumps(summarize_pmc(*args.summarize_pmc,
-                                       (args.copy_mb or 256) << 20), indent=1))
+                                       (args.copy_mb or 256) << 20, key), indent=1))
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -524,7 +574,11 @@ def main():
         return bench_batch(args, U, W, torch)
     if args.workload == 5:
         return bench_serve(args, U, W, torch)
-    w = W.config(args.workload)
+    w = W.config(args.workload, far_mode=args.far_mode)
+    if args.far_mode == "full":
+        w.name += "_full"
+        args.steps = args.steps if args.steps_given else 100
+        args.warmup = args.warmup if args.warmup_given else 3
     nrhs = args.nrhs
     chosen = args.precision
     res = run_form(U, W, torch, w, chosen, args.basis, nrhs, args.warmup, args.steps,
@@ -536,6 +590,7 @@ def main():
                          args.steps)
 
     info, avg_us, S = res["info"], res["avg_us"], res["S"]
+    tkey = traffic_key(w.name, args.basis, nrhs, w.far_mode)
     nb_total, K, dt = res["nb_total"], args.steps, res["dt"]
     n_pairs, n_box, nu = info["n_pairs"], info["n_boxes"], info["n_u"]
     s_bytes = 0 if S is None else S.nbytes
@@ -556,18 +611,18 @@ def main():
         ach = (issued if split else flops) / (avg_us[1] * 1e-6) / 1e12
         roof = {"kernel": translate_kernel, "bound": "mfma", "achieved": ach,
                 "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": measured_traffic(translate_kernel)}
+                "traffic": measured_traffic(translate_kernel, tkey)}
     else:
         b = bytes_agg if dom == 0 else bytes_dis
         ach = b / (avg_us[dom] * 1e-6) / 1e9
         roof = {"kernel": stage_names[dom], "bound": "hbm", "achieved": ach,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                "traffic": measured_traffic(stage_names[dom])}
+                "traffic": measured_traffic(stage_names[dom], tkey)}
     stages = {name: {"avg_us": float(avg_us[i])} for i, name in enumerate(stage_names)}
     stages["translate"].update(
         kernel=translate_kernel, algorithmic_flops=flops,
         tflops=trans_tflops, frac_fp32_mfma_peak=trans_tflops / PEAK_FP32_MFMA_TFLOPS,
-        traffic=measured_traffic(translate_kernel))
+        traffic=measured_traffic(translate_kernel, tkey))
     if split:
         itf = issued / (avg_us[1] * 1e-6) / 1e12
         stages["translate"].update(issued_bf16_flops=issued, issued_tflops=itf,
@@ -576,7 +631,7 @@ def main():
         st = stages[name]
         st["algorithmic_bytes"] = b
         st["gbs"] = b / (st["avg_us"] * 1e-6) / 1e9
-        st["traffic"] = measured_traffic(name)
+        st["traffic"] = measured_traffic(name, tkey)
 
     out = {
         "metric": "far-zone MVMs/s", "value": res["value"], "unit": "MVM/s",
@@ -606,10 +661,18 @@ def main():
             "translate_speedup_of_chosen": float(ot[1] / avg_us[1]),
         }
     if not args.no_cpu_baseline:
-        cb, rel = cpu_baseline(w, res["nb_ptr"], S, res["x0"], res["y0"], args.cpu_seconds)
+        if w.far_mode == "full":
+            cb, rel = cpu_baseline_sampled(w, res["nb_ptr"], S, res["x0"], res["y0"],
+                                           args.cpu_seconds, n_pairs)
+        else:
+            cb, rel = cpu_baseline(w, res["nb_ptr"], S, res["x0"], res["y0"], args.cpu_seconds)
         out["cpu_baseline"] = cb
-        out["rel_l2_vs_oracle"] = rel
-        if other is not None:
+        out["rel_l2_vs_oracle" + ("_sampled" if w.far_mode == "full" else "")] = rel
+        if other is not None and w.far_mode == "full":
+            _, orel = cpu_baseline_sampled(w, other["nb_ptr"], other["S"], other["x0"],
+                                           other["y0"], args.cpu_seconds, n_pairs)
+            out["compare"]["rel_l2_vs_oracle_sampled"] = orel
+        elif other is not None:
             import oracle as O
             yref = O.far_mvm(other["x0"].astype(np.complex128), w.boxes, w.a, w.k, w.n_d,
                              other["nb_ptr"], None if other["S"] is None

@@ -22,7 +22,7 @@ ARCH = "gfx950"
 HOST_SOURCES = ["plan.cpp", "capi.cpp", "solver.cpp"]
 HIP_SOURCES = ["kernels.hip", "gmres.hip"]
 
-HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-Wextra",
+HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-pthread", "-Wall", "-Wextra",
               "-Wno-unused-parameter", "-D__HIP_PLATFORM_AMD__",
               f"-I{ROCM}/include", f"-I{os.path.join(ROOT, 'include')}"]
 # Packed FP32 VALU instructions are disabled for all device code.
@@ -51,7 +51,7 @@ def build(verbose: bool = True) -> str:
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs,
-          f"-L{ROCM}/lib", "-lamdhip64"])
+          f"-L{ROCM}/lib", "-lamdhip64", "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

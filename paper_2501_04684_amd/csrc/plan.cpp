@@ -8,6 +8,7 @@
 #include <cstring>
 #include <limits>
 #include <mutex>
+#include <thread>
 #include <numeric>
 #include <unordered_map>
 
@@ -91,6 +92,7 @@ void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<doub
     for (const auto& g : G) mx = std::max({mx, std::abs(g.real()), std::abs(g.imag())});
     const int e = mx > 0.0 ? std::ilogb(mx) - 14 : 0;
     *scale = (float)std::ldexp(1.0, e);
+    const double inv = std::ldexp(1.0, -e);  // exact power of two
     const uint16_t zero = 0;
     const size_t plane = (size_t)P.nu * P.khb;
     uint16_t* base = (uint16_t*)dst;
@@ -98,7 +100,7 @@ void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<doub
     for (int u = 0; u < P.nu; ++u)
       for (int v = 0; v < P.nu; ++v) {
         const std::complex<double> g = G[(size_t)u * P.nu + v];
-        const float parts[2] = {(float)std::ldexp(g.real(), -e), (float)std::ldexp(g.imag(), -e)};
+        const float parts[2] = {(float)(g.real() * inv), (float)(g.imag() * inv)};
         for (int c = 0; c < 2; ++c) {
           const uint16_t hi = fp16_bits(parts[c]);
           const uint16_t lo = fp16_bits(parts[c] - fp16_value(hi));
@@ -225,20 +227,38 @@ std::vector<double> site_offsets(double a, int n_d) {
 
 void operator_fp64(const int32_t w[3], double a, double k, double eta, int n_d,
                    std::vector<std::complex<double>>& G) {
-  const std::vector<double> r = site_offsets(a, n_d);
+  // The sites form one uniform lattice of step a / n_d, so r_l - r_s depends
+  // only on the lattice difference d = m_l - m_s in [-(n_d-1), n_d-1]^3:
+  // evaluate D once per difference, then fill the site-pair blocks.
   const int nd3 = n_d * n_d * n_d, nu = 3 * nd3;
+  const int span = 2 * n_d - 1;
+  const double step = a / n_d;
+  std::vector<std::complex<double>> Dd((size_t)span * span * span * 9);
+  for (int dx = 0; dx < span; ++dx)
+    for (int dy = 0; dy < span; ++dy)
+      for (int dz = 0; dz < span; ++dz) {
+        const double R[3] = {a * w[0] + step * (dx - (n_d - 1)),
+                             a * w[1] + step * (dy - (n_d - 1)),
+                             a * w[2] + step * (dz - (n_d - 1))};
+        std::complex<double> D[3][3];
+        dyadic_green(R, k, eta, D);
+        std::complex<double>* out = &Dd[(((size_t)dx * span + dy) * span + dz) * 9];
+        for (int al = 0; al < 3; ++al)
+          for (int be = 0; be < 3; ++be) out[3 * al + be] = D[al][be];
+      }
   G.assign((size_t)nu * nu, 0.0);
-  std::complex<double> D[3][3];
-  for (int l = 0; l < nd3; ++l)
+  for (int l = 0; l < nd3; ++l) {
+    const int lx = l / (n_d * n_d), ly = (l / n_d) % n_d, lz = l % n_d;
     for (int s = 0; s < nd3; ++s) {
-      const double R[3] = {a * w[0] + r[3 * l] - r[3 * s],
-                           a * w[1] + r[3 * l + 1] - r[3 * s + 1],
-                           a * w[2] + r[3 * l + 2] - r[3 * s + 2]};
-      dyadic_green(R, k, eta, D);
+      const int sx = s / (n_d * n_d), sy = (s / n_d) % n_d, sz = s % n_d;
+      const std::complex<double>* D =
+          &Dd[((((size_t)(lx - sx + n_d - 1)) * span + (ly - sy + n_d - 1)) * span +
+               (lz - sz + n_d - 1)) * 9];
       for (int al = 0; al < 3; ++al)
         for (int be = 0; be < 3; ++be)
-          G[(size_t)(3 * l + al) * nu + 3 * s + be] = D[al][be];
+          G[(size_t)(3 * l + al) * nu + 3 * s + be] = D[3 * al + be];
     }
+  }
 }
 
 // The four wavefronts of a group work on one chunk at a time, so a group's
@@ -465,14 +485,30 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   else
     P.table.assign((size_t)n_off * img_bytes / sizeof(float), 0.0f);
   char* table = P.split() ? (char*)P.table_bf16.data() : (char*)P.table.data();
-  std::vector<std::complex<double>> G;
   P.off_scale.assign(n_off, 1.0f);
-  for (int64_t o = 0; o < n_off; ++o) {
-    char* dst = table + (size_t)o * img_bytes;
-    if (!image_cache_get(P, &P.offsets[3 * o], dst, img_bytes, &P.off_scale[o])) {
-      offset_image(P, &P.offsets[3 * o], G, dst, &P.off_scale[o]);
-      image_cache_put(P, &P.offsets[3 * o], dst, img_bytes, P.off_scale[o]);
+  // Offsets are independent: large tables (FULL far sets have one operator
+  // per distinct offset, ~10^5 on a few-thousand-box scatterer) are built
+  // on several host threads, each over a contiguous range of offsets.
+  auto build_range = [&](int64_t lo, int64_t hi) {
+    std::vector<std::complex<double>> G;
+    for (int64_t o = lo; o < hi; ++o) {
+      char* dst = table + (size_t)o * img_bytes;
+      if (!image_cache_get(P, &P.offsets[3 * o], dst, img_bytes, &P.off_scale[o])) {
+        offset_image(P, &P.offsets[3 * o], G, dst, &P.off_scale[o]);
+        image_cache_put(P, &P.offsets[3 * o], dst, img_bytes, P.off_scale[o]);
+      }
     }
+  };
+  const int64_t kPerThread = 1024;
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int64_t nthr = std::min<int64_t>(std::min(hw, 16), (n_off + kPerThread - 1) / kPerThread);
+  if (nthr <= 1) {
+    build_range(0, n_off);
+  } else {
+    std::vector<std::thread> pool;
+    for (int64_t t = 0; t < nthr; ++t)
+      pool.emplace_back(build_range, n_off * t / nthr, n_off * (t + 1) / nthr);
+    for (auto& th : pool) th.join();
   }
   return std::string();
 }
