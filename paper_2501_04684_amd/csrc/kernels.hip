@@ -31,11 +31,17 @@ __device__ inline float bf16_f(unsigned b) { return __uint_as_float(b << 16); }
 __device__ inline unsigned short f16_rn(float f) { return __half_as_ushort(__float2half_rn(f)); }
 __device__ inline float f16_f(unsigned short b) { return __half2float(__ushort_as_half(b)); }
 
+// Index of part `part` (0 re.hi, 1 im.hi, 2 re.lo, 3 im.lo) of coefficient
+// u in a 16-bit box vector: groups of 8 coefficients (one matrix-core
+// k-step) interleave the four parts, [re.hi(8) im.hi(8) re.lo(8) im.lo(8)],
+// so the two lanes holding a column's K halves read adjacent 16 bytes.
+__device__ inline int q16(int part, int u) { return 32 * (u >> 3) + 8 * part + (u & 7); }
+
 // Writes one box-vector coefficient (re, im) at index u of a box vector
 // starting at Pb. mode 0: FP32 layout [re(kh) | im(kh)]. Otherwise the
-// 16-bit layout [re.hi | re.lo | im.hi | im.lo] of khb values each, with
-// hi = round(v), lo = round(v - hi): mode 1 in BF16; mode 2 in FP16 of
-// v * inv_scale (the box vector's power-of-two scale).
+// 16-bit layout of q16 (khb coefficients), with hi = round(v),
+// lo = round(v - hi): mode 1 in BF16; mode 2 in FP16 of v * inv_scale (the
+// box vector's power-of-two scale).
 __device__ inline void put_coef(float* Pb, int u, float re, float im, int kh, int khb,
                                 int mode, float inv_scale = 1.f) {
   if (mode == 0) {
@@ -46,19 +52,19 @@ __device__ inline void put_coef(float* Pb, int u, float re, float im, int kh, in
   unsigned short* q = reinterpret_cast<unsigned short*>(Pb);
   if (mode == 1) {
     const unsigned rh = bf16_rne(re), ih = bf16_rne(im);
-    q[u] = (unsigned short)rh;
-    q[khb + u] = (unsigned short)bf16_rne(re - bf16_f(rh));
-    q[2 * khb + u] = (unsigned short)ih;
-    q[3 * khb + u] = (unsigned short)bf16_rne(im - bf16_f(ih));
+    q[q16(0, u)] = (unsigned short)rh;
+    q[q16(2, u)] = (unsigned short)bf16_rne(re - bf16_f(rh));
+    q[q16(1, u)] = (unsigned short)ih;
+    q[q16(3, u)] = (unsigned short)bf16_rne(im - bf16_f(ih));
     return;
   }
   re *= inv_scale;  // exact: a power of two
   im *= inv_scale;
   const unsigned short rh = f16_rn(re), ih = f16_rn(im);
-  q[u] = rh;
-  q[khb + u] = f16_rn(re - f16_f(rh));
-  q[2 * khb + u] = ih;
-  q[3 * khb + u] = f16_rn(im - f16_f(ih));
+  q[q16(0, u)] = rh;
+  q[q16(2, u)] = f16_rn(re - f16_f(rh));
+  q[q16(1, u)] = ih;
+  q[q16(3, u)] = f16_rn(im - f16_f(ih));
 }
 
 // Power-of-two scale bringing a box vector's largest |Re|, |Im| to
@@ -83,6 +89,39 @@ __device__ inline float wave_sum(float v) {
 __device__ inline int xcd_chunk(int bid, int grid) {
   const int per = grid >> 3;
   return (bid & 7) * per + (bid >> 3);
+}
+
+// Partial rows of one 32x32 accumulator block (32 columns of a wavefront,
+// rows m0..m0+31 of each column's partial row) are written through a
+// per-wavefront LDS tile: the block's D layout gives a lane 4-row pieces of
+// one column, so direct stores touch 32 rows per instruction; after the
+// transpose, lane l stores 16 bytes of column (l / 8) + 8 * it, and one
+// store instruction covers 8 columns x 128 contiguous bytes. Columns'
+// destination rows (within the RHS's block `part_rhs`) are taken from their
+// owning lanes; absent columns (c >= ncol) and rows at or past `pstr` are
+// not stored (masked stores). The tile pitch of 36 floats keeps the
+// 16-byte writes conflict-free. LDS accesses of one wavefront execute in
+// order, so the tile needs no barrier.
+constexpr int kTilePitch = 36;
+__device__ inline void store_block_transposed(float* tile, const floatx16& acc, float sc,
+                                              int dst, int ncol, float* __restrict__ part_rhs,
+                                              int pstr, int m0) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4)
+    *reinterpret_cast<floatx4*>(tile + r * kTilePitch + 8 * q4 + 4 * h) =
+        floatx4{acc[4 * q4], acc[4 * q4 + 1], acc[4 * q4 + 2], acc[4 * q4 + 3]} * sc;
+  const int seg = lane & 7;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int c = (lane >> 3) + 8 * it;
+    const floatx4 v = *reinterpret_cast<const floatx4*>(tile + c * kTilePitch + 4 * seg);
+    const int m = m0 + 4 * seg;
+    const int row = __shfl(dst, c, 64);  // column c's destination row
+    if (c < ncol && m + 4 <= pstr)
+      *reinterpret_cast<floatx4*>(part_rhs + (int64_t)row * pstr + m) = v;
+  }
 }
 
 // ---------------------------------------------------------------- layout
@@ -136,12 +175,12 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(
     if (mode == 0) {
       out[t] = make_float2(Pb[u], Pb[kh + u]);
     } else if (mode == 1) {
-      out[t] = make_float2(bf16_f(q[u]) + bf16_f(q[khb + u]),
-                           bf16_f(q[2 * khb + u]) + bf16_f(q[3 * khb + u]));
+      out[t] = make_float2(bf16_f(q[q16(0, u)]) + bf16_f(q[q16(2, u)]),
+                           bf16_f(q[q16(1, u)]) + bf16_f(q[q16(3, u)]));
     } else {
       const float sc = box_scale[row];
-      out[t] = make_float2((f16_f(q[u]) + f16_f(q[khb + u])) * sc,
-                           (f16_f(q[2 * khb + u]) + f16_f(q[3 * khb + u])) * sc);
+      out[t] = make_float2((f16_f(q[q16(0, u)]) + f16_f(q[q16(2, u)])) * sc,
+                           (f16_f(q[q16(1, u)]) + f16_f(q[q16(3, u)])) * sc);
     }
   }
 }
@@ -455,7 +494,8 @@ struct Mfma16<true> {
 // Work layout, pipelining and stores are those of translate_mfma_kernel:
 // lane l owns column l % 32 and K half h = l / 32; a k-step covers 8
 // consecutive values of each half (KHB = NU rounded up to 8, zero padded),
-// read as one 16-byte value per lane; the operator's four planes (re.hi,
+// read as one 16-byte value per lane from the box vector's 64-byte k-step
+// group (the two lanes of a column read adjacent 16 bytes); the operator's four planes (re.hi,
 // re.lo, im.hi, im.lo) sit in LDS and -Gi is a sign flip. 32-row blocks
 // cover all 2*NU rows (padding rows read row 0 and are not stored).
 template <int NU, bool F16, int NPROD>
@@ -477,6 +517,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   constexpr int N4 = 4 * PLANE * 2 / 16; // 16-byte units per operator
   constexpr int LD = (N4 + kBlock - 1) / kBlock;
   __shared__ uintx4 lds4[N4];
+  __shared__ floatx4 tiles4[4][32 * kTilePitch / 4];  // one per wavefront
   const unsigned short* lds = reinterpret_cast<const unsigned short*>(lds4);
 
   const int group = xcd_chunk(blockIdx.x, gridDim.x);
@@ -514,14 +555,14 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   int src0 = pair_src[i0], dst0 = pair_dst[i0];
   int src1 = pair_src[i1], dst1 = pair_dst[i1];
 
+  // k-step g of a box vector is 64 bytes: hi of both halves, then lo of both
   vec16 bh[NGB], bl[NPROD == 3 ? NGB : 1];
   {
-    const vec16* pv = reinterpret_cast<const vec16*>(
-        P + ((int64_t)rhs * n_box + src0) * VSTR + h * KHB);
+    const vec16* pv = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src0) * VSTR);
 #pragma unroll
     for (int g = 0; g < NGB; ++g) {
-      bh[g] = pv[g];
-      if (NPROD == 3) bl[g] = pv[NGB + g];
+      bh[g] = pv[4 * g + h];
+      if (NPROD == 3) bl[g] = pv[4 * g + 2 + h];
     }
   }
   // FP16: the scale of the current chunk's column (this lane's source box)
@@ -548,8 +589,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
     const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
     const int64_t i2 = min((int64_t)b2 + col0 + r, last);
-    const vec16* pv1 = reinterpret_cast<const vec16*>(
-        P + ((int64_t)rhs * n_box + src1) * VSTR + h * KHB);
+    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src1) * VSTR);
     if (F16) bsc1 = box_scale[(int64_t)rhs * n_box + src1];
     int src2, dst2;
 
@@ -581,32 +621,23 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_l[rb], bh[g], acc[rb]);
         }
-        bh[g] = pv1[g];  // next chunk
-        if (NPROD == 3) bl[g] = pv1[NGB + g];
+        bh[g] = pv1[4 * g + h];  // next chunk
+        if (NPROD == 3) bl[g] = pv1[4 * g + 2 + h];
       }
       src2 = pair_src[i2];
       dst2 = pair_dst[i2];
 
-      const int64_t row = (col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
-      float* out = part + row * PSTR;
       const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
+      float* tile = reinterpret_cast<float*>(tiles4[wave]);
+      float* part_rhs = part + (int64_t)rhs * n_pairs * PSTR;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          const int r0 = rb * 32 + 8 * q4 + 4 * h;
-          if (rb * 32 + 8 * q4 + 8 <= PSTR) {  // same for both halves h
-            floatx4 v = floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
-                                acc[rb][4 * q4 + 3]};
-            if (F16) v *= sc;
-            *reinterpret_cast<floatx4*>(out + r0) = v;
-          }
-        }
+        store_block_transposed(tile, acc[rb], sc, dst0, n0 - col0, part_rhs, PSTR, rb * 32);
     } else {  // no column of this chunk for this wavefront: fetch the next
 #pragma unroll
       for (int g = 0; g < NGB; ++g) {
-        bh[g] = pv1[g];
-        if (NPROD == 3) bl[g] = pv1[NGB + g];
+        bh[g] = pv1[4 * g + h];
+        if (NPROD == 3) bl[g] = pv1[4 * g + 2 + h];
       }
       src2 = pair_src[i2];
       dst2 = pair_dst[i2];
