@@ -4,6 +4,8 @@
 // and padded in the workspace: [re(N_u), 0.. | im(N_u), 0..], 2*kh floats
 // per box (kh = N_u + 1 rounded up to even), which is also the K-axis
 // layout the matrix-core translation consumes.
+#include <algorithm>
+
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -141,13 +143,14 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(
   }
 }
 
-// FP16 forms: one wavefront per box vector (row); its scale needs the
-// vector's largest component first. nu <= 128.
-__global__ __launch_bounds__(64) void pack_f16_kernel(
+// FP16 forms: one wavefront per box vector (row), four per workgroup; the
+// vector's scale needs its largest component first. nu <= 128.
+__global__ __launch_bounds__(kBlock) void pack_f16_kernel(
     const float2* __restrict__ x, float* __restrict__ P, float* __restrict__ box_scale,
-    int nu, int khb) {
-  const int64_t row = blockIdx.x;
-  const int l = threadIdx.x;
+    int nu, int khb, int64_t n_rows) {
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= n_rows) return;  // whole wavefronts
+  const int l = threadIdx.x & 63;
   const float2 v0 = l < nu ? x[row * nu + l] : make_float2(0.f, 0.f);
   const float2 v1 = l + 64 < nu ? x[row * nu + l + 64] : make_float2(0.f, 0.f);
   float m = fmaxf(fmaxf(fabsf(v0.x), fabsf(v0.y)), fmaxf(fabsf(v1.x), fabsf(v1.y)));
@@ -944,6 +947,158 @@ __global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
   }
 }
 
+// Stage 3 of the whole product when T_j = S_j^T and E_j comes from the
+// partial rows: a persistent pipeline over boxes. Each workgroup walks the
+// boxes blockIdx.x, + gridDim.x, ...; for box b it sums b's partial rows
+// (already in registers), stages b's first batch of S_b columns into LDS
+// (already in registers), then issues the loads of the next box into the
+// same registers and applies b while they are in flight. Columns beyond
+// the first batch are streamed afterwards (rare). Same arithmetic and
+// summation order as disaggregate_kernel.
+template <int EQ>
+__global__ __launch_bounds__(kBlock, 2) void disaggregate_pipe_kernel(
+    const float* __restrict__ part, const int32_t* __restrict__ test_ptr, int64_t n_pairs,
+    const int64_t* __restrict__ nb_ptr, const float2* __restrict__ S,
+    float2* __restrict__ y, int64_t n_box, int64_t nb_total, int nu, int kh) {
+  constexpr int LD = ((kStage + 1) / 2 + kBlock - 1) / kBlock;
+  constexpr int PU = 8;
+  __shared__ float4 Es4[98];
+  __shared__ float4 stage4[(kStage + 1) / 2];  // S batch, or the row-sum scratch
+  const float* Es = reinterpret_cast<const float*>(Es4);
+  const float2* stage = reinterpret_cast<const float2*>(stage4);
+  floatx4* stagev = reinterpret_cast<floatx4*>(stage4);
+  const int r = blockIdx.y;
+  const int t = threadIdx.x;
+  float2* yb = y + (int64_t)r * nb_total;
+  const int CB = (kStage - 2) / nu;
+  const int R4 = kh / 2, H = kBlock / R4, g = t % R4, h = t / R4;
+  const float4* pr = reinterpret_cast<const float4*>(part) + (int64_t)r * n_pairs * R4;
+  const int q = (t & 63) >> 4;
+
+  // the box whose loads are in flight, and the loads themselves
+  int64_t start = 0, nb = 0;
+  int p0 = 0, p1 = 0, shift = 0, lim = 0, n4 = 0, lo = 0, hi = 0;
+  floatx4 tmp[LD];
+  float2 edge0 = make_float2(0.f, 0.f), edge1 = make_float2(0.f, 0.f);
+  float4 pv[PU];
+  auto issue = [&](int64_t b) {
+    start = nb_ptr[b];
+    nb = nb_ptr[b + 1] - start;
+    p0 = test_ptr[b];
+    p1 = test_ptr[b + 1];
+    if (nb > 0) {  // uniform
+      const int ncol = (int)min((int64_t)CB, nb);
+      const float2* blk = S + start * nu;
+      shift = (reinterpret_cast<uintptr_t>(blk) & 15) ? 1 : 0;
+      lim = ncol * nu + shift;
+      n4 = (lim + 1) / 2;
+      lo = shift;
+      hi = (lim & 1) ? n4 - 2 : n4 - 1;
+      const float2* s2 = blk - shift;
+      const floatx4* s4 = reinterpret_cast<const floatx4*>(s2);
+#pragma unroll
+      for (int it = 0; it < LD; ++it) tmp[it] = s4[min(max(t + it * kBlock, lo), hi)];
+      edge0 = s2[shift ? 1 : 2 * lo];
+      edge1 = s2[(lim & 1) ? 2 * (n4 - 1) : 2 * hi];
+      if (h < H && p1 > p0) {
+#pragma unroll
+        for (int i = 0; i < PU; ++i) pv[i] = pr[(int64_t)min(p0 + h + i * H, p1 - 1) * R4 + g];
+      }
+    }
+  };
+
+  int64_t b = blockIdx.x;
+  if (b >= n_box) return;
+  issue(b);
+  for (; b < n_box; b += gridDim.x) {
+    const int64_t cstart = start, cnb = nb;
+    const int cp0 = p0, cp1 = p1, cshift = shift, clim = lim, cn4 = n4, clo = lo, chi = hi;
+    __syncthreads();  // the previous box is done with the LDS
+    if (cnb > 0) {
+      // E_b: this box's partial rows, first PU per row group from registers
+      float4* scratch = stage4;
+      if (h < H) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (cp1 > cp0) {
+#pragma unroll
+          for (int i = 0; i < PU; ++i)
+            if (cp0 + h + i * H < cp1) {
+              acc.x += pv[i].x;
+              acc.y += pv[i].y;
+              acc.z += pv[i].z;
+              acc.w += pv[i].w;
+            }
+        }
+#pragma unroll 4
+        for (int p = cp0 + h + PU * H; p < cp1; p += H) {
+          const float4 v = pr[(int64_t)p * R4 + g];
+          acc.x += v.x;
+          acc.y += v.y;
+          acc.z += v.z;
+          acc.w += v.w;
+        }
+        scratch[h * R4 + g] = acc;
+      }
+      __syncthreads();
+      for (int m4 = t; m4 < R4; m4 += kBlock) {
+        float4 s4 = scratch[m4];
+        for (int hh = 1; hh < H; ++hh) {
+          const float4 v = scratch[hh * R4 + m4];
+          s4.x += v.x;
+          s4.y += v.y;
+          s4.z += v.z;
+          s4.w += v.w;
+        }
+        Es4[m4] = s4;
+      }
+      __syncthreads();
+      // S_b's first batch into LDS
+#pragma unroll
+      for (int it = 0; it < LD; ++it) {
+        const int i = t + it * kBlock;
+        if (i >= clo && i <= chi) stagev[i] = tmp[it];
+      }
+      if (t == 0 && cshift) stagev[0] = floatx4{0.f, 0.f, edge0.x, edge0.y};
+      if (t == 1 && (clim & 1)) stagev[cn4 - 1] = floatx4{edge1.x, edge1.y, 0.f, 0.f};
+    }
+    float er[EQ], ei[EQ];
+#pragma unroll
+    for (int i = 0; i < EQ; ++i) {
+      const int u = min(q + 4 * i, nu - 1);
+      er[i] = Es[u];
+      ei[i] = Es[nu + u];
+    }
+    // the next box's loads go out before this box is applied
+    if (b + gridDim.x < n_box) issue(b + gridDim.x);
+    __syncthreads();
+    if (cnb <= 0) continue;
+    const int ncol = (int)min((int64_t)CB, cnb);
+    apply_staged<EQ>(stage, cshift, ncol, er, ei, nu, yb + cstart);
+    for (int64_t c0 = CB; c0 < cnb; c0 += CB) {  // more than CB functions (rare)
+      __syncthreads();
+      const int nc = (int)min((int64_t)CB, cnb - c0);
+      const float2* blk = S + (cstart + c0) * nu;
+      const int sh = (reinterpret_cast<uintptr_t>(blk) & 15) ? 1 : 0;
+      const int lm = nc * nu + sh;
+      const int m4n = (lm + 1) / 2;
+      const int l0 = sh, h0 = (lm & 1) ? m4n - 2 : m4n - 1;
+      const float2* s2 = blk - sh;
+      const floatx4* s4 = reinterpret_cast<const floatx4*>(s2);
+      for (int i = l0 + t; i <= h0; i += kBlock) stagev[i] = s4[i];
+      if (t == 0 && sh) {
+        const float2 v = s2[1];
+        stagev[0] = floatx4{0.f, 0.f, v.x, v.y};
+      }
+      if (t == 1 && (lm & 1)) {
+        const float2 v = s2[2 * (m4n - 1)];
+        stagev[m4n - 1] = floatx4{v.x, v.y, 0.f, 0.f};
+      }
+      __syncthreads();
+      apply_staged<EQ>(stage, sh, nc, er, ei, nu, yb + cstart + c0);
+    }
+  }
+}
+
 int grid_for(int64_t total) {
   const int64_t g = (total + kBlock - 1) / kBlock;
   return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
@@ -958,8 +1113,9 @@ bool translate_uses_mfma(const Plan& p) {
 int launch_pack(const Plan& p, const void* x, float* P, int nrhs, void* stream) {
   const int64_t rows = (int64_t)nrhs * p.n_box;
   if (p.fp16()) {
-    hipLaunchKernelGGL(pack_f16_kernel, dim3((unsigned)rows), dim3(64), 0, (hipStream_t)stream,
-                       (const float2*)x, P, p.d_box_scale, p.nu, p.khb);
+    hipLaunchKernelGGL(pack_f16_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(kBlock), 0,
+                       (hipStream_t)stream, (const float2*)x, P, p.d_box_scale, p.nu, p.khb,
+                       rows);
     return (int)hipGetLastError();
   }
   hipLaunchKernelGGL(pack_kernel, dim3(grid_for(rows * (p.split() ? p.khb : p.kh))),
@@ -1053,7 +1209,13 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
                      p.d_test_ptr, p.n_pairs(), (const float2*)E, p.d_nb_ptr,     \
                      (const float2*)p.d_S, (const float2*)p.d_T, mode, (float2*)y, \
                      p.n_box, nb_total, p.nu, p.kh)
-  if (from_parts) {
+  if (from_parts && mode == 1 && small) {
+    // persistent: two resident workgroups per compute unit
+    const unsigned groups = (unsigned)std::min<int64_t>(p.n_box, 2 * 256);
+    hipLaunchKernelGGL((disaggregate_pipe_kernel<21>), dim3(groups, nrhs), dim3(kBlock), 0, s,
+                       part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S,
+                       (float2*)y, p.n_box, nb_total, p.nu, p.kh);
+  } else if (from_parts) {
     if (small) UBF_DISAGG(true, 21); else UBF_DISAGG(true, 49);
   } else {
     if (small) UBF_DISAGG(false, 21); else UBF_DISAGG(false, 49);
