@@ -1209,7 +1209,10 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
                      p.d_test_ptr, p.n_pairs(), (const float2*)E, p.d_nb_ptr,     \
                      (const float2*)p.d_S, (const float2*)p.d_T, mode, (float2*)y, \
                      p.n_box, nb_total, p.nu, p.kh)
-  if (from_parts && mode == 1 && small) {
+  // The pipeline pays off while a box's partial rows are few (interaction
+  // lists: tens per box); with thousands per box (FULL far sets) the row
+  // sums dominate and want every workgroup the grid can hold.
+  if (from_parts && mode == 1 && small && p.n_pairs() <= 40 * p.n_box) {
     // persistent: two resident workgroups per compute unit
     const unsigned groups = (unsigned)std::min<int64_t>(p.n_box, 2 * 256);
     hipLaunchKernelGGL((disaggregate_pipe_kernel<21>), dim3(groups, nrhs), dim3(kBlock), 0, s,
