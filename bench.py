@@ -49,6 +49,10 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E peak
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_04684_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_mvm_shell3338_hbm_traffic.json")
+# Stage events are recorded on one product in this many inside the timed
+# loop: an event costs a few microseconds of device time, about a tenth
+# of a product when all four are recorded on every product.
+PROFILE_EVERY = 8
 # Stage-2 forms: (dtype label, BF16/FP16 products per pair or 0 for FP32)
 FORMS = {"split-bf16": ("f32 (stage 2 bf16 hi/lo x3, f32 accumulation)", 3),
          "split-fp16": ("f32 (stage 2 fp16 hi/lo x3, scaled, f32 accumulation)", 3),
@@ -271,19 +275,20 @@ def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0):
         U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
     torch.cuda.synchronize()
 
-    U.profile_begin(ff.plan, steps)
+    n_rec = -(-steps // PROFILE_EVERY)
+    U.profile_begin(ff.plan, n_rec, PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
         U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stage_ms, call_ms = U.profile_end(ff.plan, steps)
+    stage_ms, call_ms = U.profile_end(ff.plan, n_rec)
 
     U.far_mvm(ff.plan, X[0], Y, nrhs, stream)  # first vector, for accuracy
     torch.cuda.synchronize()
     out = {"info": ff.info, "plan_ms": plan_ms, "dt": dt, "value": steps * nrhs / dt,
-           "avg_us": stage_ms / steps * 1e3, "call_ms": call_ms,
+           "avg_us": stage_ms / len(call_ms) * 1e3, "call_ms": call_ms,
            "y0": Y.cpu().numpy(), "x0": X[0].cpu().numpy(), "nb_ptr": nb_ptr, "S": S,
            "nb_total": nb_total}
     ff.close()
@@ -456,7 +461,8 @@ def bench_serve(args, U, W, torch):
             for i, d in enumerate(specs)]
     total = torch.cuda.get_device_properties(0).total_memory
     budget = int(min(200 << 30, 0.7 * total))
-    srv = S.Server(hbm_budget=budget, max_active=16, steps_per_tick=2, profile=True)
+    srv = S.Server(hbm_budget=budget, max_active=16, steps_per_tick=2, profile=True,
+                   profile_every=PROFILE_EVERY)
     # warm-up request (not counted): loads kernels, fills the operator cache
     wb = W.mask_boxes(600, 0.5, 1)
     warm = S.Request(-1, wb, W.complex_normal((1, len(wb) * 81), 1), tol=tol,

@@ -328,18 +328,24 @@ int ubf_plan_far_pairs(const ubf_plan* plan, int32_t* test, int32_t* src,
  * Errors: UBF_EINVAL (null, o out of range). */
 int ubf_plan_operator(const ubf_plan* plan, int32_t o, double* out);
 
-/* Measurement support (not part of the method). Record HIP timing events
- * on the call's stream before and after each of the three stages of the
- * next max_calls products on this plan, whether issued by ubf_far_mvm or
- * by a GMRES solver on the plan (products beyond that are not recorded).
- * Errors: UBF_EINVAL (max_calls < 1), UBF_EDEVICE. */
-int ubf_profile_begin(ubf_plan* plan, int32_t max_calls);
+/* Measurement support (not part of the method). Time the kernel of each
+ * of the three stages of products on this plan, whether issued by
+ * ubf_far_mvm or by a GMRES solver on the plan: the kernel's dispatch
+ * itself records a HIP event when it starts and one when it ends
+ * (hipExtLaunchKernel), so a stage's time is its kernel's execution time
+ * alone. Products recorded: the 1st, (every+1)-th, (2*every+1)-th ...
+ * after this call, up to max_calls of them. A recorded dispatch costs
+ * more device time than a plain one, so every > 1 keeps the recording's
+ * cost off a throughput measurement.
+ * Errors: UBF_EINVAL (max_calls < 1, every < 1), UBF_EDEVICE. */
+int ubf_profile_begin(ubf_plan* plan, int32_t max_calls, int32_t every);
 
 /* Wait for the recorded calls and release their events. stage_ms (3
- * doubles, may be NULL) receives the summed elapsed milliseconds of stage
+ * doubles, may be NULL) receives the summed kernel milliseconds of stage
  * 1, 2 and 3; call_ms (may be NULL, room for max_calls floats) receives
- * each call's first-to-last event time; *n_calls (may be NULL) the number
- * of calls recorded. Errors: UBF_ESTATE (no profile begun), UBF_EDEVICE. */
+ * each call's time from the start of stage 1 to the end of stage 3;
+ * *n_calls (may be NULL) the number of calls recorded.
+ * Errors: UBF_ESTATE (no profile begun), UBF_EDEVICE. */
 int ubf_profile_end(ubf_plan* plan, double* stage_ms, float* call_ms,
                     int32_t* n_calls);
 

@@ -96,7 +96,7 @@ _SIGS = {
     "ubf_plan_offsets": (ctypes.c_int, [_VP, _VP]),
     "ubf_plan_far_pairs": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ubf_plan_operator": (ctypes.c_int, [_VP, _I32, _VP]),
-    "ubf_profile_begin": (ctypes.c_int, [_VP, _I32]),
+    "ubf_profile_begin": (ctypes.c_int, [_VP, _I32, _I32]),
     "ubf_profile_end": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ubf_gmres_workspace_bytes": (_SZ, [_VP, _I32, _I32]),
     "ubf_gmres_create": (ctypes.c_int, [_VP, _I32, _I32, ctypes.c_double, ctypes.c_double,
@@ -298,9 +298,10 @@ def plan_operator(plan, o: int) -> np.ndarray:
     return out
 
 
-def profile_begin(plan, max_calls: int):
-    """Start recording per-stage HIP events for the next far_mvm calls."""
-    _check(lib().ubf_profile_begin(plan, int(max_calls)), "ubf_profile_begin")
+def profile_begin(plan, max_calls: int, every: int = 1):
+    """Start recording per-stage HIP events for one in ``every`` of the
+    next products on the plan (at most ``max_calls`` recorded)."""
+    _check(lib().ubf_profile_begin(plan, int(max_calls), int(every)), "ubf_profile_begin")
 
 
 def profile_end(plan, max_calls: int):

@@ -35,16 +35,16 @@ const std::string& last_error_text() { return g_last_error; }
 
 int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStream_t s,
                 hipEvent_t* ev) {
-  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  int e = launch_aggregate(p, d_x, p.d_P, nrhs, s);
+  const StageEvents st[3] = {{ev ? ev[0] : nullptr, ev ? ev[1] : nullptr},
+                             {ev ? ev[2] : nullptr, ev ? ev[3] : nullptr},
+                             {ev ? ev[4] : nullptr, ev ? ev[5] : nullptr}};
+  int e = launch_aggregate(p, d_x, p.d_P, nrhs, s, ev ? &st[0] : nullptr);
   if (e) return hip_fail(e, "aggregate launch");
-  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  e = launch_translate(p, p.d_P, p.d_part, nrhs, s);
+  e = launch_translate(p, p.d_P, p.d_part, nrhs, s, ev ? &st[1] : nullptr);
   if (e) return hip_fail(e, "translate launch");
-  if (ev && hipEventRecord(ev[2], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
-  e = launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, s);
+  e = launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, s, false,
+                          ev ? &st[2] : nullptr);
   if (e) return hip_fail(e, "disaggregate launch");
-  if (ev && hipEventRecord(ev[3], s) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
   return ok();
 }
 
@@ -348,14 +348,15 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
   return ok();
 }
 
-int ubf_profile_begin(ubf_plan* plan, int32_t max_calls) {
+int ubf_profile_begin(ubf_plan* plan, int32_t max_calls, int32_t every) {
   if (!plan) return fail(UBF_EINVAL, "plan is NULL");
   if (max_calls < 1) return fail(UBF_EINVAL, "max_calls must be >= 1");
+  if (every < 1) return fail(UBF_EINVAL, "every must be >= 1");
   for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
   plan->events.clear();
   plan->profiling = false;
-  plan->events.reserve(4 * (size_t)max_calls);
-  for (size_t i = 0; i < 4 * (size_t)max_calls; ++i) {
+  plan->events.reserve(ubf_plan::kEventsPerCall * (size_t)max_calls);
+  for (size_t i = 0; i < ubf_plan::kEventsPerCall * (size_t)max_calls; ++i) {
     hipEvent_t e;
     hipError_t err = hipEventCreate(&e);
     if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
@@ -363,6 +364,8 @@ int ubf_profile_begin(ubf_plan* plan, int32_t max_calls) {
   }
   plan->prof_max = max_calls;
   plan->prof_n = 0;
+  plan->prof_every = every;
+  plan->prof_seen = 0;
   plan->profiling = true;
   return ok();
 }
@@ -374,17 +377,17 @@ int ubf_profile_end(ubf_plan* plan, double* stage_ms, float* call_ms,
   plan->profiling = false;
   double sum[3] = {0, 0, 0};
   for (int32_t c = 0; c < plan->prof_n; ++c) {
-    hipEvent_t* ev = &plan->events[4 * (size_t)c];
-    hipError_t err = hipEventSynchronize(ev[3]);
+    hipEvent_t* ev = &plan->events[ubf_plan::kEventsPerCall * (size_t)c];
+    hipError_t err = hipEventSynchronize(ev[5]);
     if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize");
     for (int st = 0; st < 3; ++st) {
       float ms = 0.f;
-      err = hipEventElapsedTime(&ms, ev[st], ev[st + 1]);
+      err = hipEventElapsedTime(&ms, ev[2 * st], ev[2 * st + 1]);
       if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
       sum[st] += ms;
     }
     if (call_ms) {
-      err = hipEventElapsedTime(&call_ms[c], ev[0], ev[3]);
+      err = hipEventElapsedTime(&call_ms[c], ev[0], ev[5]);
       if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
     }
   }

@@ -11,10 +11,14 @@
 
 struct ubf_plan {
   ubf::Plan p;
-  // Stage timing (ubf_profile_begin/end): 4 events per recorded call.
+  // Stage timing (ubf_profile_begin/end): a start and a stop event per
+  // stage of each recorded call, one call in prof_every recorded.
+  static constexpr size_t kEventsPerCall = 6;
   std::vector<hipEvent_t> events;
   int32_t prof_max = 0;
   int32_t prof_n = 0;
+  int32_t prof_every = 1;
+  int64_t prof_seen = 0;
   bool profiling = false;
   // Captured three-stage product (ubf_plan_capture / ubf_plan_replay).
   hipGraph_t graph = nullptr;
@@ -23,7 +27,8 @@ struct ubf_plan {
   // Events for the next recorded product, or NULL when not profiling.
   hipEvent_t* next_events() {
     if (!profiling || prof_n >= prof_max) return nullptr;
-    return &events[4 * (size_t)prof_n++];
+    if (prof_seen++ % prof_every != 0) return nullptr;
+    return &events[kEventsPerCall * (size_t)prof_n++];
   }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);

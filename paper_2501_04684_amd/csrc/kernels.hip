@@ -6,6 +6,7 @@
 // layout the matrix-core translation consumes.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -1099,6 +1100,24 @@ __global__ __launch_bounds__(kBlock, 2) void disaggregate_pipe_kernel(
   }
 }
 
+// Launch with the stage's timing events when it has them.
+#define UBF_LAUNCH(EV, KERNEL, GRID, BLOCK, STREAM, ...)                                 \
+  do {                                                                                  \
+    if (EV)                                                                             \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, (EV)->start, (EV)->stop, 0, \
+                            __VA_ARGS__);                                               \
+    else                                                                                \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                  \
+  } while (0)
+
+// A stage with nothing to launch still completes its events.
+int record_empty(const StageEvents* ev, hipStream_t s) {
+  if (!ev) return 0;
+  hipError_t e = hipEventRecord(ev->start, s);
+  if (e == hipSuccess) e = hipEventRecord(ev->stop, s);
+  return (int)e;
+}
+
 int grid_for(int64_t total) {
   const int64_t g = (total + kBlock - 1) / kBlock;
   return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
@@ -1110,17 +1129,17 @@ bool translate_uses_mfma(const Plan& p) {
   return p.nu == 81 || p.nu == 24 || p.nu == 3;
 }
 
-int launch_pack(const Plan& p, const void* x, float* P, int nrhs, void* stream) {
+int launch_pack(const Plan& p, const void* x, float* P, int nrhs, void* stream,
+                const StageEvents* ev) {
   const int64_t rows = (int64_t)nrhs * p.n_box;
   if (p.fp16()) {
-    hipLaunchKernelGGL(pack_f16_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(kBlock), 0,
-                       (hipStream_t)stream, (const float2*)x, P, p.d_box_scale, p.nu, p.khb,
-                       rows);
+    UBF_LAUNCH(ev, pack_f16_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(kBlock),
+               (hipStream_t)stream, (const float2*)x, P, p.d_box_scale, p.nu, p.khb, rows);
     return (int)hipGetLastError();
   }
-  hipLaunchKernelGGL(pack_kernel, dim3(grid_for(rows * (p.split() ? p.khb : p.kh))),
-                     dim3(kBlock), 0, (hipStream_t)stream, (const float2*)x, P, rows,
-                     p.nu, p.kh, p.khb, p.split() ? 1 : 0);
+  UBF_LAUNCH(ev, pack_kernel, dim3(grid_for(rows * (p.split() ? p.khb : p.kh))), dim3(kBlock),
+             (hipStream_t)stream, (const float2*)x, P, rows, p.nu, p.kh, p.khb,
+             p.split() ? 1 : 0);
   return (int)hipGetLastError();
 }
 
@@ -1132,28 +1151,29 @@ int launch_unpack(const Plan& p, const float* P, void* out, int nrhs, void* stre
   return (int)hipGetLastError();
 }
 
-int launch_aggregate(const Plan& p, const void* x, float* P, int nrhs, void* stream) {
-  if (!p.has_basis) return launch_pack(p, x, P, nrhs, stream);
-  hipLaunchKernelGGL(aggregate_kernel, dim3((unsigned)p.n_box, nrhs), dim3(kBlock), 0,
-                     (hipStream_t)stream, (const float2*)x, p.d_nb_ptr,
-                     (const float2*)p.d_S, P, p.n_box, p.nb_total(), p.nu, p.kh,
-                     p.khb, p.fp16() ? 2 : (p.split() ? 1 : 0), p.d_box_scale);
+int launch_aggregate(const Plan& p, const void* x, float* P, int nrhs, void* stream,
+                     const StageEvents* ev) {
+  if (!p.has_basis) return launch_pack(p, x, P, nrhs, stream, ev);
+  UBF_LAUNCH(ev, aggregate_kernel, dim3((unsigned)p.n_box, nrhs), dim3(kBlock),
+             (hipStream_t)stream, (const float2*)x, p.d_nb_ptr, (const float2*)p.d_S, P,
+             p.n_box, p.nb_total(), p.nu, p.kh, p.khb, p.fp16() ? 2 : (p.split() ? 1 : 0),
+             p.d_box_scale);
   return (int)hipGetLastError();
 }
 
 int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
-                     void* stream) {
+                     void* stream, const StageEvents* ev) {
   const int nch = (int)p.n_chunks();
-  if (nch == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
+  if (nch == 0) return record_empty(ev, s);
   const dim3 groups((unsigned)p.n_groups(), nrhs);
   const int64_t trash = (int64_t)p.max_nrhs * p.n_pairs();
   if (p.split()) {
     const unsigned short* tb = reinterpret_cast<const unsigned short*>(p.d_table);
 #define UBF_SPLIT(NU, F16, NPROD)                                                         \
-  hipLaunchKernelGGL((translate_split_kernel<NU, F16, NPROD>), groups, dim3(kBlock), 0, s, \
-                     tb, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,      \
-                     p.n_box, p.n_pairs(), trash, p.d_off_scale, p.d_box_scale)
+  UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD>), groups, dim3(kBlock), s, tb,      \
+             p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,         \
+             p.n_pairs(), trash, p.d_off_scale, p.d_box_scale)
 #define UBF_SPLIT_NU(F16, NPROD)                           \
   switch (p.nu) {                                          \
     case 81: UBF_SPLIT(81, F16, NPROD); break;             \
@@ -1174,50 +1194,47 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
   }
   switch (p.nu) {
     case 81:
-      hipLaunchKernelGGL(translate_mfma_kernel<81>, groups, dim3(kBlock), 0, s,
-                         p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs(), trash);
+      UBF_LAUNCH(ev, translate_mfma_kernel<81>, groups, dim3(kBlock), s, p.d_table, p.d_chunks,
+                 p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box, p.n_pairs(), trash);
       break;
     case 24:
-      hipLaunchKernelGGL(translate_mfma_kernel<24>, groups, dim3(kBlock), 0, s,
-                         p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs(), trash);
+      UBF_LAUNCH(ev, translate_mfma_kernel<24>, groups, dim3(kBlock), s, p.d_table, p.d_chunks,
+                 p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box, p.n_pairs(), trash);
       break;
     case 3:
-      hipLaunchKernelGGL(translate_mfma_kernel<3>, groups, dim3(kBlock), 0, s,
-                         p.d_table, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part,
-                         p.n_box, p.n_pairs(), trash);
+      UBF_LAUNCH(ev, translate_mfma_kernel<3>, groups, dim3(kBlock), s, p.d_table, p.d_chunks,
+                 p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box, p.n_pairs(), trash);
       break;
     default:
-      hipLaunchKernelGGL(translate_generic_kernel, dim3((unsigned)nch, nrhs),
-                         dim3(kBlock), 0, s, p.d_table, p.d_chunks, p.d_pair_src,
-                         p.d_pair_dst, P, part, p.n_box, p.n_pairs(), p.nu, p.kh);
+      UBF_LAUNCH(ev, translate_generic_kernel, dim3((unsigned)nch, nrhs), dim3(kBlock), s,
+                 p.d_table, p.d_chunks, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
+                 p.n_pairs(), p.nu, p.kh);
   }
   return (int)hipGetLastError();
 }
 
 int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
                         const void* E, void* y, int nrhs, void* stream,
-                        bool identity) {
+                        bool identity, const StageEvents* ev) {
   const int mode = (identity || !p.has_basis) ? 0 : (p.d_T ? 2 : 1);
   const int64_t nb_total = mode == 0 ? p.n_box * (int64_t)p.nu : p.nb_total();
   const dim3 grid((unsigned)p.n_box, nrhs);
   hipStream_t s = (hipStream_t)stream;
   const bool small = p.nu <= 84;  // at most 21 rows of E_j per lane
 #define UBF_DISAGG(PARTS, EQ)                                                     \
-  hipLaunchKernelGGL((disaggregate_kernel<PARTS, EQ>), grid, dim3(kBlock), 0, s, part, \
-                     p.d_test_ptr, p.n_pairs(), (const float2*)E, p.d_nb_ptr,     \
-                     (const float2*)p.d_S, (const float2*)p.d_T, mode, (float2*)y, \
-                     p.n_box, nb_total, p.nu, p.kh)
+  UBF_LAUNCH(ev, (disaggregate_kernel<PARTS, EQ>), grid, dim3(kBlock), s, part,        \
+             p.d_test_ptr, p.n_pairs(), (const float2*)E, p.d_nb_ptr,                 \
+             (const float2*)p.d_S, (const float2*)p.d_T, mode, (float2*)y, p.n_box,    \
+             nb_total, p.nu, p.kh)
   // The pipeline pays off while a box's partial rows are few (interaction
   // lists: tens per box); with thousands per box (FULL far sets) the row
   // sums dominate and want every workgroup the grid can hold.
   if (from_parts && mode == 1 && small && p.n_pairs() <= 40 * p.n_box) {
     // persistent: two resident workgroups per compute unit
     const unsigned groups = (unsigned)std::min<int64_t>(p.n_box, 2 * 256);
-    hipLaunchKernelGGL((disaggregate_pipe_kernel<21>), dim3(groups, nrhs), dim3(kBlock), 0, s,
-                       part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S,
-                       (float2*)y, p.n_box, nb_total, p.nu, p.kh);
+    UBF_LAUNCH(ev, (disaggregate_pipe_kernel<21>), dim3(groups, nrhs), dim3(kBlock), s, part,
+               p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
+               p.n_box, nb_total, p.nu, p.kh);
   } else if (from_parts) {
     if (small) UBF_DISAGG(true, 21); else UBF_DISAGG(true, 49);
   } else {

@@ -137,11 +137,13 @@ class Server:
     ``hbm_budget``: device bytes the active requests may hold together;
     ``max_active``: concurrent requests (each on its own stream);
     ``steps_per_tick``: Arnoldi steps enqueued for a request each time its
-    previous steps have completed.
+    previous steps have completed; ``profile``: record HIP events around
+    the stages of one product in ``profile_every`` of each request.
     """
 
     def __init__(self, hbm_budget: int, max_active: int = 16, steps_per_tick: int = 2,
-                 plan_threads: int = 8, device: str = "cuda", profile: bool = False):
+                 plan_threads: int = 8, device: str = "cuda", profile: bool = False,
+                 profile_every: int = 1):
         import torch
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
@@ -151,7 +153,8 @@ class Server:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.max_active)]
         self.log = []          # (time, n_active, bytes in use) after each admission/release
         self.peak_active = 0
-        self.profile = bool(profile)  # HIP events around each product's stages
+        self.profile = bool(profile)  # HIP events around the stages of products
+        self.profile_every = max(1, int(profile_every))
 
     def close(self):
         self.pool.shutdown(wait=True)
@@ -167,7 +170,7 @@ class Server:
                         stream=stream)
         sigma = req.sigma if req.sigma is not None else auto_shift(solver)
         if self.profile:
-            profile_begin(ff.plan, self._max_products(req))
+            profile_begin(ff.plan, self._max_products(req), self.profile_every)
         b = torch.from_numpy(np.ascontiguousarray(req.b)).to(self.device)
         x = torch.empty_like(b)
         stream.wait_stream(torch.cuda.current_stream())

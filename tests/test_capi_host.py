@@ -70,7 +70,7 @@ def test_null_arguments_rejected_before_any_device_call():
     assert L.ubf_plan_bind(None, None, 0, 1, None) == -1
     assert L.ubf_far_mvm(None, None, None, 1, None) == -1
     assert L.ubf_plan_info(None, None) == -1
-    assert L.ubf_profile_begin(None, 1) == -1
+    assert L.ubf_profile_begin(None, 1, 1) == -1
     assert L.ubf_profile_end(None, None, None, None) == -1
     plan = U.plan_create(W.grid_boxes(2, 2, 2), A, K, 2)
     try:
@@ -85,7 +85,8 @@ def test_null_arguments_rejected_before_any_device_call():
         assert L.ubf_plan_bind(plan, 1 << 20, 1 << 30, 0, None) == -1
         assert L.ubf_workspace_bytes(plan, 0) == 0
         assert L.ubf_plan_operator(plan, 10 ** 6, None) == -1
-        assert L.ubf_profile_begin(plan, 0) == -1
+        assert L.ubf_profile_begin(plan, 0, 1) == -1
+        assert L.ubf_profile_begin(plan, 1, 0) == -1
         assert L.ubf_profile_end(plan, None, None, None) == -4
     finally:
         U.plan_destroy(plan)
