@@ -181,6 +181,33 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
 int ubf_plan_set_basis(ubf_plan* plan, const int64_t* nb_ptr,
                        const void* d_S, const void* d_T);
 
+/* Bytes of the device image that ubf_plan_set_networks fills for networks
+ * of `hidden` units; 0 if the plan's box size or the width has no network
+ * kernel (n_d must be 2, 3 or 4; 1 <= hidden <= 64). */
+size_t ubf_network_bytes(const ubf_plan* plan, int32_t hidden);
+
+/* Let trained networks stand in for the translation operators (Sec. 3,
+ * Fig. 5): stage 2 then adds, for each far-zone pair (i -> j) with offset
+ * w, the network output ||P_i|| (W2_w CReLU(W1_w P_i/||P_i|| + b1_w) +
+ * b2_w) to E_j, where ||.|| is the largest modulus (l-infinity norm) of the
+ * box vector, CReLU(z) = max(Re z, 0) + j max(Im z, 0) per component, and
+ * a zero box vector contributes zero. Stages 1 and 3 are unchanged.
+ * Weights, complex64 on the device, one network per distinct offset in the
+ * order of ubf_plan_offsets: d_W1 [n_offsets][hidden][N_u] (row-major),
+ * d_b1 [n_offsets][hidden], d_W2 [n_offsets][N_u][hidden], d_b2
+ * [n_offsets][N_u]. They are converted on hip_stream into d_net (caller
+ * owned, 16-byte aligned, at least ubf_network_bytes(plan, hidden) bytes),
+ * which must stay allocated while the plan uses it; the weight arrays may
+ * be freed once the stream has passed this call. hidden = 0 (pointers
+ * ignored) returns stage 2 to the operator table. Needs a bound plan of
+ * the FP32 form (precision 0). Any captured graph is discarded.
+ * Errors: UBF_EINVAL (null, precision, n_d or hidden out of range,
+ * misaligned image), UBF_ENOMEM (image too small), UBF_ESTATE (unbound),
+ * UBF_EDEVICE. */
+int ubf_plan_set_networks(ubf_plan* plan, int32_t hidden, const void* d_W1, const void* d_b1,
+                          const void* d_W2, const void* d_b2, void* d_net, size_t net_bytes,
+                          void* hip_stream);
+
 /* The whole far-zone product y = T G S x (Algorithm 5) for nrhs vectors.
  * d_x, d_y: [nrhs][sum N_b] complex64 (identity basis: sum N_b =
  * n_boxes*N_u); y is overwritten. 1 <= nrhs <= the bound max_nrhs.

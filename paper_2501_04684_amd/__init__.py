@@ -22,7 +22,7 @@ __all__ = [
     "library_path",
     "declared_symbols", "plan_create", "plan_create_batch", "workspace_bytes",
     "plan_bind", "plan_capture", "plan_replay", "plan_tune",
-    "plan_set_basis", "far_mvm", "aggregate", "translate", "disaggregate",
+    "plan_set_basis", "network_bytes", "plan_set_networks", "far_mvm", "aggregate", "translate", "disaggregate",
     "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
     "profile_begin", "profile_end", "plan_destroy", "status_string",
     "last_error", "FarField", "gmres_workspace_bytes", "gmres_create", "gmres_start",
@@ -85,6 +85,8 @@ _SIGS = {
     "ubf_workspace_bytes": (_SZ, [_VP, _I32]),
     "ubf_plan_bind": (ctypes.c_int, [_VP, _VP, _SZ, _I32, _VP]),
     "ubf_plan_set_basis": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ubf_network_bytes": (_SZ, [_VP, _I32]),
+    "ubf_plan_set_networks": (ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "ubf_far_mvm": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
     "ubf_plan_capture": (ctypes.c_int, [_VP, _VP, _VP, _I32]),
     "ubf_plan_replay": (ctypes.c_int, [_VP, _VP]),
@@ -223,6 +225,28 @@ def plan_set_basis(plan, nb_ptr=None, S=None, T=None):
     nb = np.ascontiguousarray(np.asarray(nb_ptr, dtype=np.int64))
     _check(lib().ubf_plan_set_basis(plan, nb.ctypes.data, _dev_ptr(S), _dev_ptr(T)),
            "ubf_plan_set_basis")
+
+
+def network_bytes(plan, hidden: int) -> int:
+    """Bytes of the device image for networks of ``hidden`` units (0: none)."""
+    return int(lib().ubf_network_bytes(plan, int(hidden)))
+
+
+def plan_set_networks(plan, hidden, W1=None, b1=None, W2=None, b2=None, image=None,
+                      stream=None):
+    """Per-offset networks (complex64 device tensors in plan offset order:
+    W1 [n_off][hidden][N_u], b1 [n_off][hidden], W2 [n_off][N_u][hidden],
+    b2 [n_off][N_u]) packed into ``image`` (a device tensor of at least
+    network_bytes(plan, hidden) bytes, kept by the caller); hidden = 0
+    returns stage 2 to the operator table."""
+    if int(hidden) == 0:
+        _check(lib().ubf_plan_set_networks(plan, 0, None, None, None, None, None, 0, None),
+               "ubf_plan_set_networks")
+        return
+    nbytes = image.numel() * image.element_size()
+    _check(lib().ubf_plan_set_networks(plan, int(hidden), _dev_ptr(W1), _dev_ptr(b1),
+                                       _dev_ptr(W2), _dev_ptr(b2), _dev_ptr(image), nbytes,
+                                       _stream(stream)), "ubf_plan_set_networks")
 
 
 def _nrhs(x, nrhs):
@@ -429,6 +453,32 @@ class FarField:
         self._basis = (S, T)  # keep the device matrices alive
         self.nb_total = (int(np.asarray(nb_ptr)[-1]) if nb_ptr is not None
                          else self.info["n_boxes"] * self.info["n_u"])
+
+    def set_networks(self, W1=None, b1=None, W2=None, b2=None):
+        """Let per-offset networks (Sec. 3) stand in for the operators in
+        stage 2; arguments as for ``plan_set_networks`` (numpy arrays or
+        tensors, moved to the device as complex64). No arguments: back to
+        the operator table."""
+        import torch
+        if W1 is None:
+            plan_set_networks(self.plan, 0)
+            self._networks = None
+            return
+        dev = self.workspace.device
+        W1, b1, W2, b2 = (torch.as_tensor(t).to(device=dev, dtype=torch.complex64).contiguous()
+                          for t in (W1, b1, W2, b2))
+        n_off, hidden, n_u = W1.shape
+        if (n_off != self.info["n_offsets"] or n_u != self.info["n_u"]
+                or tuple(b1.shape) != (n_off, hidden) or tuple(W2.shape) != (n_off, n_u, hidden)
+                or tuple(b2.shape) != (n_off, n_u)):
+            raise ValueError("network shapes do not match the plan's offsets and N_u")
+        nbytes = network_bytes(self.plan, hidden)
+        if nbytes == 0:
+            raise ValueError(f"no network kernel for N_u={n_u}, hidden={hidden}")
+        image = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+        plan_set_networks(self.plan, hidden, W1, b1, W2, b2, image)
+        torch.cuda.current_stream(dev).synchronize()  # the weights may go now
+        self._networks = image
 
     def __call__(self, x, out=None, stream=None):
         import torch

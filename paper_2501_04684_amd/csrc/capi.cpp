@@ -9,6 +9,7 @@
 
 #include "capi_internal.hpp"
 #include "kernels.hpp"
+#include "networks.hpp"
 
 namespace ubf {
 
@@ -33,6 +34,13 @@ int hip_fail(int err, const char* what) {
 
 const std::string& last_error_text() { return g_last_error; }
 
+// Stage 2 by the operator table or, when the plan has networks, by them.
+int launch_stage2(const Plan& p, const float* P, float* part, int nrhs, hipStream_t s,
+                  const StageEvents* ev) {
+  return p.hidden > 0 ? launch_translate_cvfcnn(p, P, part, nrhs, s, ev)
+                      : launch_translate(p, P, part, nrhs, s, ev);
+}
+
 int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStream_t s,
                 hipEvent_t* ev) {
   const StageEvents st[3] = {{ev ? ev[0] : nullptr, ev ? ev[1] : nullptr},
@@ -40,7 +48,7 @@ int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStre
                              {ev ? ev[4] : nullptr, ev ? ev[5] : nullptr}};
   int e = launch_aggregate(p, d_x, p.d_P, nrhs, s, ev ? &st[0] : nullptr);
   if (e) return hip_fail(e, "aggregate launch");
-  e = launch_translate(p, p.d_P, p.d_part, nrhs, s, ev ? &st[1] : nullptr);
+  e = launch_stage2(p, p.d_P, p.d_part, nrhs, s, ev ? &st[1] : nullptr);
   if (e) return hip_fail(e, "translate launch");
   e = launch_disaggregate(p, true, p.d_part, nullptr, d_y, nrhs, s, false,
                           ev ? &st[2] : nullptr);
@@ -423,7 +431,7 @@ int ubf_translate(ubf_plan* plan, const void* d_P, void* d_E, int32_t nrhs,
   // Stage 2 alone maps box vectors to box vectors whatever the basis.
   int e = ubf::launch_pack(p, d_P, p.d_P, nrhs, hip_stream);
   if (e) return hip_fail(e, "pack launch");
-  e = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, hip_stream);
+  e = ubf::launch_stage2(p, p.d_P, p.d_part, nrhs, (hipStream_t)hip_stream, nullptr);
   if (e) return hip_fail(e, "translate launch");
   e = ubf::launch_disaggregate(p, true, p.d_part, nullptr, d_E, nrhs, hip_stream,
                                /*identity=*/true);
@@ -440,6 +448,44 @@ int ubf_disaggregate(ubf_plan* plan, const void* d_E, void* d_y, int32_t nrhs,
   const ubf::Plan& p = plan->p;
   int e = ubf::launch_disaggregate(p, false, nullptr, d_E, d_y, nrhs, hip_stream);
   if (e) return hip_fail(e, "disaggregate launch");
+  return ok();
+}
+
+size_t ubf_network_bytes(const ubf_plan* plan, int32_t hidden) {
+  if (!plan || !ubf::network_shape_supported(plan->p.nu, hidden)) return 0;
+  return ubf::network_image_bytes(plan->p, hidden);
+}
+
+int ubf_plan_set_networks(ubf_plan* plan, int32_t hidden, const void* d_W1, const void* d_b1,
+                          const void* d_W2, const void* d_b2, void* d_net, size_t net_bytes,
+                          void* hip_stream) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  ubf::Plan& p = plan->p;
+  if (hidden == 0) {  // back to the operator table
+    plan->drop_graph();
+    p.hidden = 0;
+    p.d_net = nullptr;
+    return ok();
+  }
+  if (!p.ws) return fail(UBF_ESTATE, "plan is not bound");
+  if (p.precision != 0) return fail(UBF_EINVAL, "networks need the FP32 form (precision 0)");
+  if (hidden < 0 || hidden > ubf::kMaxHidden)
+    return fail(UBF_EINVAL, "hidden must be in 1.." + std::to_string(ubf::kMaxHidden));
+  if (!ubf::network_shape_supported(p.nu, hidden))
+    return fail(UBF_EINVAL, "networks need n_d 2, 3 or 4 (n_u 24, 81 or 192)");
+  if (!d_W1 || !d_b1 || !d_W2 || !d_b2 || !d_net)
+    return fail(UBF_EINVAL, "weight, bias or image pointer is NULL");
+  if (((uintptr_t)d_net & 15) != 0) return fail(UBF_EINVAL, "image must be 16-byte aligned");
+  const size_t need = ubf::network_image_bytes(p, hidden);
+  if (net_bytes < need)
+    return fail(UBF_ENOMEM, "network image too small: need " + std::to_string(need) +
+                                " bytes, got " + std::to_string(net_bytes));
+  plan->drop_graph();
+  int e = ubf::launch_network_pack(p, hidden, d_W1, d_b1, d_W2, d_b2, (float*)d_net,
+                                   hip_stream);
+  if (e) return hip_fail(e, "network pack launch");
+  p.hidden = hidden;
+  p.d_net = (const float*)d_net;
   return ok();
 }
 

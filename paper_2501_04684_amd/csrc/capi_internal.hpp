@@ -52,7 +52,7 @@ int hip_fail(int err, const char* what);
 const std::string& last_error_text();
 
 // The three stages of the product y = T G S x, enqueued on `s`
-// (ev: optional 4 timing events).
+// (ev: optional timing events, a start and a stop per stage).
 int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStream_t s,
                 hipEvent_t* ev);
 

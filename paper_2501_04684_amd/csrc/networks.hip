@@ -1,0 +1,308 @@
+// Translation by complex-valued fully connected networks (Sec. 3, Fig. 5):
+// the network of a translation vector w stands in for the product G_w P_i of
+// Eq. 13, and stage 3 is unchanged. For a source box vector x (3N_d complex
+// values) with s = ||x||_inf (largest modulus) the pair's contribution is
+//   s * (W2 CReLU(W1 (x / s) + b1) + b2),
+// CReLU acting on real and imaginary parts separately; a zero vector gives
+// zero. Both layers run on v_mfma_f32_32x32x2_f32 as real products, each
+// MFMA k-step pairing a real K value (lane half 0) with the imaginary one
+// (lane half 1):
+//   [hr; hi] = [[W1r, -W1i], [W1i, W1r]] [xr; xi]   M = 2*HP, K = 2*NU
+//   [Er; Ei] = [[W2r, -W2i], [W2i, W2r]] [hr; hi]   M = 2*NU, K = 2*HP
+// with HP = the hidden width rounded up to 32 (hidden units past the
+// network's width are zero). The division by s is applied to the layer-1
+// accumulators and the product by s to the layer-2 results, so the staged
+// box vectors are used as they are.
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+#include "networks.hpp"
+
+namespace ubf {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBlock = 256;
+static_assert(kChunk == 128, "a chunk is four quarters of 32 pairs");
+
+// Network image of one offset, in floats (all parts 16-byte aligned):
+//   W1 planes (re, im) [2][HP][KH]  rows = hidden units, columns = inputs
+//   b1 (re, im)        [2][HP]
+//   W2 planes (re, im) [2][NU][HP] rows = outputs, columns = hidden units
+//   b2 (re, im)        [2][KH]
+// Entries past the network's width or NU are zero.
+__host__ __device__ constexpr int64_t image_floats(int nu, int kh, int hp) {
+  return 2LL * hp * kh + 2LL * hp + 2LL * nu * hp + 2LL * kh;
+}
+
+// Caller layout (complex64, offsets in plan order): W1 [n_off][H][NU],
+// b1 [n_off][H], W2 [n_off][NU][H], b2 [n_off][NU].
+__global__ __launch_bounds__(kBlock) void network_pack_kernel(
+    const float2* __restrict__ W1, const float2* __restrict__ b1,
+    const float2* __restrict__ W2, const float2* __restrict__ b2, float* __restrict__ img,
+    int64_t n_off, int nu, int kh, int hp, int hidden) {
+  const int64_t nf = image_floats(nu, kh, hp);
+  const int64_t w1 = 2LL * hp * kh, bb1 = 2LL * hp, w2 = 2LL * nu * hp;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_off * nf;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = t / nf;
+    int64_t i = t - o * nf;
+    float v = 0.f;
+    if (i < w1) {
+      const int64_t plane = i / ((int64_t)hp * kh), rem = i % ((int64_t)hp * kh);
+      const int64_t m = rem / kh, k = rem % kh;
+      if (m < hidden && k < nu) {
+        const float2 c = W1[(o * hidden + m) * nu + k];
+        v = plane ? c.y : c.x;
+      }
+    } else if ((i -= w1) < bb1) {
+      const int64_t plane = i / hp, m = i % hp;
+      if (m < hidden) {
+        const float2 c = b1[o * hidden + m];
+        v = plane ? c.y : c.x;
+      }
+    } else if ((i -= bb1) < w2) {
+      const int64_t plane = i / ((int64_t)nu * hp), rem = i % ((int64_t)nu * hp);
+      const int64_t u = rem / hp, m = rem % hp;
+      if (m < hidden) {
+        const float2 c = W2[(o * nu + u) * hidden + m];
+        v = plane ? c.y : c.x;
+      }
+    } else {
+      i -= w2;
+      const int64_t plane = i / kh, u = i % kh;
+      if (u < nu) {
+        const float2 c = b2[o * nu + u];
+        v = plane ? c.y : c.x;
+      }
+    }
+    img[t] = v;
+  }
+}
+
+// Largest modulus of each box vector (planar padded FP32 rows of 2*kh
+// floats), one wavefront per row.
+__global__ __launch_bounds__(kBlock) void linf_kernel(const float* __restrict__ P,
+                                                      float* __restrict__ out,
+                                                      int64_t n_rows, int nu, int kh) {
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= n_rows) return;  // whole wavefronts
+  const int l = threadIdx.x & 63;
+  const float* Pb = P + row * 2 * kh;
+  float m = 0.f;
+  for (int u = l; u < nu; u += 64) {
+    const float re = Pb[u], im = Pb[kh + u];
+    m = fmaxf(m, sqrtf(fmaf(re, re, im * im)));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if (l == 0) out[row] = m;
+}
+
+__device__ inline floatx16 mfma4(floatx4 a, floatx4 b, floatx16 acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+  return acc;
+}
+
+// One workgroup per 32 pairs of a chunk (a chunk holds up to 128 pairs of
+// one offset; blockIdx.x = 4 * chunk + quarter). The 32 source box vectors
+// are staged in LDS; wavefront w computes layer-1 row blocks w, w + 4, ...
+// (the A values of its lane's row are read from the network image, four
+// k-steps per 16-byte load, with the sign of -W1i applied on load), writes
+// bias + CReLU to the hidden tile, and after a barrier computes layer-2 row
+// blocks w, w + 4, ... the same way. Lane l owns pair column l % 32; its
+// 4-row pieces of each output block go to the pair's partial row, whose
+// positions are the output rows [Er | Ei].
+template <int NU, int HB>
+__global__ __launch_bounds__(kBlock, 2) void translate_cvfcnn_kernel(
+    const float* __restrict__ net, const int32_t* __restrict__ chunks,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
+    const float* __restrict__ P, const float* __restrict__ linf, float* __restrict__ part,
+    int64_t n_box, int64_t n_pairs, int hidden) {
+  constexpr int KH = (NU + 3) & ~3;
+  constexpr int HP = 32 * HB;
+  constexpr int64_t NF = image_floats(NU, KH, HP);
+  constexpr int B1_OFF = 2 * HP * KH;
+  constexpr int W2_OFF = B1_OFF + 2 * HP;
+  constexpr int B2_OFF = W2_OFF + 2 * NU * HP;
+  constexpr int XP = 2 * KH + 4;     // LDS pitch of a staged box vector
+  constexpr int HPT = 2 * HP + 4;    // LDS pitch of a hidden column
+  constexpr int OB = (2 * NU + 31) / 32;
+  constexpr int PSTR = 2 * KH;
+  constexpr int Q = 2 * KH / 4;      // 16-byte pieces of a box vector
+  __shared__ floatx4 xs4[32 * XP / 4];
+  __shared__ floatx4 hs4[32 * HPT / 4];
+  float* xs = reinterpret_cast<float*>(xs4);
+  float* hs = reinterpret_cast<float*>(hs4);
+
+  const int chunk = blockIdx.x >> 2;
+  const int c0 = (blockIdx.x & 3) * 32;
+  const int o = chunks[4 * chunk], begin = chunks[4 * chunk + 1];
+  const int count = chunks[4 * chunk + 2];
+  if (c0 >= count) return;  // whole workgroup
+  const int ncol = min(32, count - c0);
+  const int rhs = blockIdx.y;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const float* no = net + (size_t)o * NF;
+  const float* Pr = P + (int64_t)rhs * n_box * 2 * KH;
+
+  for (int i = t; i < 32 * Q; i += kBlock) {
+    const int c = i / Q, q = i - c * Q;
+    floatx4 v = {0.f, 0.f, 0.f, 0.f};
+    if (c < ncol) {
+      const int src = pair_src[begin + c0 + c];
+      v = reinterpret_cast<const floatx4*>(Pr + (int64_t)src * 2 * KH)[q];
+    }
+    xs4[c * (XP / 4) + q] = v;
+  }
+  const bool live = r < ncol;
+  const int pos = begin + c0 + min(r, ncol - 1);
+  const int src = pair_src[pos];
+  const int dst = pair_dst[pos];
+  const float s = linf[(int64_t)rhs * n_box + src];
+  const float inv_s = s > 0.f ? 1.f / s : 0.f;
+  __syncthreads();
+
+  // layer 1: A row = hidden unit m of part (0: real, 1: imaginary);
+  // lane half h multiplies the real (h = 0) or imaginary (h = 1) inputs
+  for (int rb = wave; rb < 2 * HB; rb += 4) {
+    const int hpart = rb / HB;
+    const int m0 = (rb % HB) * 32;
+    const int plane = hpart == 0 ? h : 1 - h;
+    const float sgn = (hpart == 0 && h == 1) ? -1.f : 1.f;
+    const floatx4* arow =
+        reinterpret_cast<const floatx4*>(no + ((size_t)plane * HP + m0 + r) * KH);
+    const floatx4* brow = reinterpret_cast<const floatx4*>(xs + r * XP + h * KH);
+    floatx16 acc = {};
+#pragma unroll 4
+    for (int g = 0; g < KH / 4; ++g) acc = mfma4(arow[g] * sgn, brow[g], acc);
+    const float* b1 = no + B1_OFF + hpart * HP + m0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      floatx4 v;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int row = 8 * q + 4 * h + jj;
+        const float z = fmaf(acc[4 * q + jj], inv_s, b1[row]);
+        v[jj] = (m0 + row < hidden) ? fmaxf(z, 0.f) : 0.f;
+      }
+      *reinterpret_cast<floatx4*>(hs + r * HPT + rb * 32 + 8 * q + 4 * h) = v;
+    }
+  }
+  __syncthreads();
+
+  // layer 2: A row = output row of [Er | Ei]; padding rows (>= 2 NU) read
+  // row 0 and are not stored
+  float* prow = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
+  for (int ob = wave; ob < OB; ob += 4) {
+    const int row = ob * 32 + r;
+    const int opart = (row >= NU && row < 2 * NU) ? 1 : 0;
+    const int u = row < NU ? row : (row < 2 * NU ? row - NU : 0);
+    const int plane = opart == 0 ? h : 1 - h;
+    const float sgn = (opart == 0 && h == 1) ? -1.f : 1.f;
+    const floatx4* arow =
+        reinterpret_cast<const floatx4*>(no + W2_OFF + ((size_t)plane * NU + u) * HP);
+    const floatx4* brow = reinterpret_cast<const floatx4*>(hs + r * HPT + h * HP);
+    floatx16 acc = {};
+#pragma unroll 4
+    for (int g = 0; g < HP / 4; ++g) acc = mfma4(arow[g] * sgn, brow[g], acc);
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r0 = ob * 32 + 8 * q + 4 * h;  // first of this lane's 4 rows
+        if (r0 < 2 * NU) {
+          floatx4 v;
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int orow = r0 + jj;
+            const float b = orow < NU ? no[B2_OFF + orow]
+                                      : (orow < 2 * NU ? no[B2_OFF + KH + orow - NU] : 0.f);
+            v[jj] = s * (acc[4 * q + jj] + b);
+          }
+          *reinterpret_cast<floatx4*>(prow + r0) = v;
+        }
+      }
+    }
+  }
+}
+
+int grid_for(int64_t total) {
+  const int64_t g = (total + kBlock - 1) / kBlock;
+  return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
+
+}  // namespace
+
+bool network_shape_supported(int nu, int hidden) {
+  return (nu == 24 || nu == 81 || nu == 192) && hidden >= 1 && hidden <= kMaxHidden;
+}
+
+int network_hp(int hidden) { return hidden <= 32 ? 32 : 64; }
+
+size_t network_image_bytes(const Plan& p, int hidden) {
+  return (size_t)std::max<int32_t>(p.n_off(), 1) *
+         (size_t)image_floats(p.nu, p.kh, network_hp(hidden)) * sizeof(float);
+}
+
+int launch_network_pack(const Plan& p, int hidden, const void* W1, const void* b1,
+                        const void* W2, const void* b2, float* img, void* stream) {
+  const int hp = network_hp(hidden);
+  const int64_t total = (int64_t)p.n_off() * image_floats(p.nu, p.kh, hp);
+  if (total == 0) return 0;
+  hipLaunchKernelGGL(network_pack_kernel, dim3(grid_for(total)), dim3(kBlock), 0,
+                     (hipStream_t)stream, (const float2*)W1, (const float2*)b1,
+                     (const float2*)W2, (const float2*)b2, img, (int64_t)p.n_off(), p.nu,
+                     p.kh, hp, hidden);
+  return (int)hipGetLastError();
+}
+
+// Launch with timing events when the stage has them (plain launch otherwise,
+// as under graph capture).
+#define UBF_LAUNCH(T0, T1, KERNEL, GRID, STREAM, ...)                                     \
+  do {                                                                                   \
+    if ((T0) || (T1))                                                                    \
+      hipExtLaunchKernelGGL(KERNEL, GRID, dim3(kBlock), 0, STREAM, T0, T1, 0, __VA_ARGS__); \
+    else                                                                                 \
+      hipLaunchKernelGGL(KERNEL, GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__);            \
+  } while (0)
+
+int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs, void* stream,
+                            const StageEvents* ev) {
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t rows = (int64_t)nrhs * p.n_box;
+  const int nch = (int)p.n_chunks();
+  hipEvent_t t0 = ev ? ev->start : nullptr, t1 = ev ? ev->stop : nullptr;
+  hipEvent_t t_linf = nch == 0 ? t1 : nullptr;
+  UBF_LAUNCH(t0, t_linf, linf_kernel, dim3((unsigned)((rows + 3) / 4)), s, P, p.d_box_scale,
+             rows, p.nu, p.kh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nch == 0) return (int)e;
+  const dim3 grid((unsigned)(4 * nch), nrhs);
+  hipEvent_t none = nullptr;
+#define UBF_NET(NU, HB)                                                                    \
+  UBF_LAUNCH(none, t1, (translate_cvfcnn_kernel<NU, HB>), grid, s, p.d_net, p.d_chunks,    \
+             p.d_pair_src, p.d_pair_dst, P, p.d_box_scale, part, p.n_box, p.n_pairs(),     \
+             p.hidden)
+  const bool wide = p.hidden > 32;
+  switch (p.nu) {
+    case 24: if (wide) UBF_NET(24, 2); else UBF_NET(24, 1); break;
+    case 81: if (wide) UBF_NET(81, 2); else UBF_NET(81, 1); break;
+    case 192: if (wide) UBF_NET(192, 2); else UBF_NET(192, 1); break;
+    default: return (int)hipErrorInvalidValue;  // rejected when the networks are set
+  }
+#undef UBF_NET
+#undef UBF_LAUNCH
+  return (int)hipGetLastError();
+}
+
+}  // namespace ubf

@@ -166,6 +166,11 @@ struct Plan {
   float* d_off_scale = nullptr;  // [n_off] (FP16 forms)
   float* d_box_scale = nullptr;  // [max_nrhs][n_box] box-vector scales (FP16 forms)
 
+  // Networks standing in for the operators (Sec. 3): hidden width (0 = none,
+  // stage 2 uses the operator table) and the device image, owned by the caller.
+  int hidden = 0;
+  const float* d_net = nullptr;
+
   // Basis.
   bool has_basis = false;
   std::vector<int64_t> nb_ptr;  // n_box + 1

@@ -18,7 +18,7 @@ A, K = 0.25, 2 * np.pi
 def test_library_exports_every_declared_symbol():
     L = U.lib()
     names = U.declared_symbols()
-    assert len(names) == 30
+    assert len(names) == 32
     for name in names:
         assert hasattr(L, name), name
 
@@ -88,6 +88,31 @@ def test_null_arguments_rejected_before_any_device_call():
         assert L.ubf_profile_begin(plan, 0, 1) == -1
         assert L.ubf_profile_begin(plan, 1, 0) == -1
         assert L.ubf_profile_end(plan, None, None, None) == -4
+        # networks: unbound plan is a state error; hidden 0 always clears
+        assert L.ubf_plan_set_networks(plan, 16, 1 << 20, 1 << 20, 1 << 20, 1 << 20,
+                                       1 << 20, 1 << 30, None) == -4
+        assert L.ubf_plan_set_networks(plan, 0, None, None, None, None, None, 0, None) == 0
+    finally:
+        U.plan_destroy(plan)
+    assert L.ubf_network_bytes(None, 16) == 0
+    assert L.ubf_plan_set_networks(None, 16, None, None, None, None, None, 0, None) == -1
+
+
+@pytest.mark.parametrize("n_d,ok", [(1, False), (2, True), (3, True), (4, True)])
+def test_network_image_size(n_d, ok):
+    plan = U.plan_create(W.grid_boxes(4, 4, 2), A, K, n_d)
+    try:
+        n_off = U.plan_info(plan)["n_offsets"]
+        for hidden in (1, 32, 33, 50, 64):
+            nb = U.network_bytes(plan, hidden)
+            assert (nb > 0) == ok
+            if ok:
+                assert nb % (16 * n_off) == 0
+        # wider networks never take less room; out-of-range widths have no kernel
+        if ok:
+            assert U.network_bytes(plan, 33) > U.network_bytes(plan, 32)
+        assert U.network_bytes(plan, 0) == 0
+        assert U.network_bytes(plan, 65) == 0
     finally:
         U.plan_destroy(plan)
 

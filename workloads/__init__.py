@@ -159,6 +159,20 @@ def complex_normal(shape, seed: int, dtype=np.complex64) -> np.ndarray:
     return z.astype(dtype)
 
 
+def random_networks(n_off: int, hidden: int, n_u: int, seed: int,
+                    bias: float = 0.1) -> tuple:
+    """Seeded complex64 weights of one network per offset, shaped as the
+    library takes them: W1 (n_off, hidden, n_u) with N(0, 1/n_u) parts,
+    b1 (n_off, hidden), W2 (n_off, n_u, hidden) with N(0, 1/hidden) parts,
+    b2 (n_off, n_u); biases have N(0, bias^2) parts."""
+    W1 = complex_normal((n_off, hidden, n_u), seed) / np.float32(np.sqrt(n_u))
+    b1 = complex_normal((n_off, hidden), seed + 1) * np.float32(bias)
+    W2 = complex_normal((n_off, n_u, hidden), seed + 2) / np.float32(np.sqrt(hidden))
+    b2 = complex_normal((n_off, n_u), seed + 3) * np.float32(bias)
+    return (W1.astype(np.complex64), b1.astype(np.complex64), W2.astype(np.complex64),
+            b2.astype(np.complex64))
+
+
 def random_basis(nb: np.ndarray, n_u: int, seed: int,
                  dtype=np.complex64) -> tuple[np.ndarray, np.ndarray]:
     """Random per-box basis matrices ``S_i`` (``n_u x nb[i]``, column-major).
