@@ -53,6 +53,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_mvm_shell3338_hbm_traffic.jso
 # loop: an event costs a few microseconds of device time, about a tenth
 # of a product when all four are recorded on every product.
 PROFILE_EVERY = 8
+NETWORK_FILE = os.path.join(ROOT, "paper_2501_04684_amd", "data", "networks_nd4_h50_a0.125.npz")
 # Stage-2 forms: (dtype label, BF16/FP16 products per pair or 0 for FP32)
 FORMS = {"split-bf16": ("f32 (stage 2 bf16 hi/lo x3, f32 accumulation)", 3),
          "split-fp16": ("f32 (stage 2 fp16 hi/lo x3, scaled, f32 accumulation)", 3),
@@ -144,8 +145,9 @@ def parse():
     ap.add_argument("--far-mode", choices=["ilist", "full"], default="ilist",
                     help="far set of workloads 1-3: the interaction list, or every pair "
                          "with Chebyshev offset >= 2 (FULL)")
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
-                    help="synthetic workload index (2 = 3,338-box shell)")
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5, 6],
+                    help="synthetic workload index (2 = 3,338-box shell; 6 = the "
+                         "2-wavelength sphere with trained translation networks)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -201,6 +203,141 @@ def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
                   f"(NumPy FP64, grouped by offset; {len(os.sched_getaffinity(0))} "
                   f"host cores visible, {cpu_model})",
     }, rel
+
+
+def cpu_baseline_networks(w, weights, offsets, x0, y0_net, y0_table, budget_s):
+    """Oracle leg of the network workload: the oracle's network translation
+    (the same expanded weights) timed on the host, parity of the GPU result
+    with it, and the error of networks and operator table against the
+    oracle's FP64 DGFA product (the networks' approximation error, Eq. 18)."""
+    import numpy as np
+    import oracle as O
+    from oracle import cvfcnn as C
+
+    nets = {tuple(int(c) for c in offsets[o]): tuple(t[o] for t in weights)
+            for o in range(len(offsets))}
+    P = x0.reshape(1, w.n_box, w.n_u).astype(np.complex128)
+    t0 = time.perf_counter()
+    n = 0
+    y_par = None
+    while True:
+        y = C.translate_cvfcnn(P, w.boxes, nets, w.far_mode).reshape(1, -1)
+        if y_par is None:
+            y_par = y
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    y_dgfa = O.far_mvm(x0.astype(np.complex128), w.boxes, w.a, w.k, w.n_d, mode=w.far_mode)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    cb = {"value": n / dt, "unit": "MVM/s", "cores": len(os.sched_getaffinity(0)),
+          "kind": "oracle",
+          "sample": f"{n} network-translation MVMs of the same workload in {dt:.1f} s "
+                    "(NumPy FP64, one matmul pair per offset)"}
+    acc = {"rel_l2_vs_oracle": rel(y0_net, y_par),
+           "network_rel_l2_vs_dgfa": rel(y0_net, y_dgfa),
+           "table_rel_l2_vs_dgfa": rel(y0_table, y_dgfa)}
+    return cb, acc
+
+
+def bench_networks(args, U, W, torch):
+    """Stage 2 by trained networks (Sec. 3; 192 -> 50 -> 192, one network per
+    offset from the 16 orbit networks) on the 2-wavelength sphere at a =
+    0.125, identity basis, then the operator table on the same plan."""
+    import numpy as np
+    from paper_2501_04684_amd import training as T
+
+    w = W.config(6)
+    if not os.path.exists(NETWORK_FILE):
+        print(f"{NETWORK_FILE} is missing: train it with python -m "
+              "paper_2501_04684_amd.training --n-d 4 --a 0.125 --hidden 50 --out ...",
+              file=sys.stderr)
+        return 1
+    orbit, meta = T.load(NETWORK_FILE)
+    hidden = int(meta["hidden"])
+    if int(meta["n_d"]) != w.n_d or abs(float(meta["a"]) - w.a) > 1e-12:
+        raise ValueError("network file does not match the workload's n_d and a")
+    dev = torch.device("cuda:0")
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode)
+    offsets = U.plan_offsets(ff.plan)
+    weights = T.networks_for_plan(ff.plan, orbit, w.n_d)
+    n = w.n_box * w.n_u
+    n_vec = 50
+    X = torch.from_numpy(W.complex_normal((n_vec, 1, n), seed=1000)).to(dev)
+    Y = torch.empty((1, n), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def timed():
+        for s in range(args.warmup):
+            U.far_mvm(ff.plan, X[s % n_vec], Y, 1, stream)
+        torch.cuda.synchronize()
+        n_rec = -(-args.steps // PROFILE_EVERY)
+        U.profile_begin(ff.plan, n_rec, PROFILE_EVERY)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            U.far_mvm(ff.plan, X[s % n_vec], Y, 1, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stage_ms, call_ms = U.profile_end(ff.plan, n_rec)
+        U.far_mvm(ff.plan, X[0], Y, 1, stream)
+        torch.cuda.synchronize()
+        return dt, stage_ms / len(call_ms) * 1e3, call_ms, Y.cpu().numpy()
+
+    ff.set_networks(*weights)
+    dt, avg_us, call_ms, y_net = timed()
+    ff.set_networks()
+    dt_t, avg_t, call_t, y_table = timed()
+    info = ff.info
+    n_pairs, nu = info["n_pairs"], info["n_u"]
+    flops = 16.0 * hidden * nu * n_pairs          # two complex layers per pair
+    hp = 32 if hidden <= 32 else 64
+    issued = 2.0 * (2 * hp) * (2 * nu) * 2 * n_pairs   # both layers, padding included
+    tr = flops / (avg_us[1] * 1e-6) / 1e12
+    stage_names = ["aggregate", "translate", "disaggregate"]
+    dom = int(np.argmax(avg_us))
+    byt = 2 * n * 8
+    if dom == 1:
+        roof = {"kernel": "translate_cvfcnn", "bound": "mfma", "achieved": tr,
+                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": tr / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
+    else:
+        ach = byt / (avg_us[dom] * 1e-6) / 1e9
+        roof = {"kernel": stage_names[dom], "bound": "hbm", "achieved": ach,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                "traffic": None}
+    out = {
+        "metric": "far-zone MVMs/s", "value": args.steps / dt, "unit": "MVM/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (network translation, FP32 matrix cores)", "data": "synthetic",
+        "config": {"workload": w.name, "n_boxes": w.n_box, "n_pairs": n_pairs,
+                   "n_offsets": info["n_offsets"], "n_u": nu, "hidden": hidden,
+                   "far_mode": w.far_mode, "basis": "identity", "nrhs": 1,
+                   "translation": "trained networks (first training stage)",
+                   "network_test_error_mean": float(np.mean([v["err_mean"]
+                                                             for v in orbit.values()]))},
+        "p50_ms": float(np.percentile(call_ms, 50)),
+        "p99_ms": float(np.percentile(call_ms, 99)),
+        "stages": {name: {"avg_us": float(avg_us[i])} for i, name in enumerate(stage_names)},
+        "roofline": roof,
+        "compare": {"translation": "operator table (FP32, generic kernel for N_u = 192)",
+                    "value": args.steps / dt_t, "translate_us": float(avg_t[1]),
+                    "speedup_of_networks": dt_t / dt,
+                    "translate_speedup_of_networks": float(avg_t[1] / avg_us[1])},
+    }
+    out["stages"]["translate"].update(kernel="translate_cvfcnn", algorithmic_flops=flops,
+                                      tflops=tr, issued_flops=issued,
+                                      frac_fp32_mfma_peak=tr / PEAK_FP32_MFMA_TFLOPS)
+    if not args.no_cpu_baseline:
+        x0 = X[0].cpu().numpy()
+        cb, acc = cpu_baseline_networks(w, weights, offsets, x0, y_net, y_table,
+                                        args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out.update(acc)
+    ff.close()
+    print(json.dumps(out))
+    return 0
 
 
 def cpu_baseline_sampled(w, nb_ptr, S, x0, y0_gpu, budget_s, n_pairs, n_sample=4):
@@ -580,6 +717,8 @@ def main():
         return bench_batch(args, U, W, torch)
     if args.workload == 5:
         return bench_serve(args, U, W, torch)
+    if args.workload == 6:
+        return bench_networks(args, U, W, torch)
     w = W.config(args.workload, far_mode=args.far_mode)
     if args.far_mode == "full":
         w.name += "_full"

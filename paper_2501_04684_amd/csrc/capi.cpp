@@ -34,11 +34,13 @@ int hip_fail(int err, const char* what) {
 
 const std::string& last_error_text() { return g_last_error; }
 
-// Stage 2 by the operator table or, when the plan has networks, by them.
+// Stage 2 by the plan's networks when it has them, else by the operator
+// table (the staged kernel for box sizes too wide for the register kernels).
 int launch_stage2(const Plan& p, const float* P, float* part, int nrhs, hipStream_t s,
                   const StageEvents* ev) {
-  return p.hidden > 0 ? launch_translate_cvfcnn(p, P, part, nrhs, s, ev)
-                      : launch_translate(p, P, part, nrhs, s, ev);
+  if (p.hidden > 0) return launch_translate_cvfcnn(p, P, part, nrhs, s, ev);
+  if (staged_translate_supported(p)) return launch_translate_staged(p, P, part, nrhs, s, ev);
+  return launch_translate(p, P, part, nrhs, s, ev);
 }
 
 int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStream_t s,
@@ -502,7 +504,7 @@ int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
   out->n_chunks = p.n_chunks();
   out->table_bytes = (int64_t)p.table_bytes();
   out->translate_flops = 8.0 * p.nu * (double)p.nu * (double)p.n_pairs();
-  out->mfma = ubf::translate_uses_mfma(p) ? 1 : 0;
+  out->mfma = (ubf::translate_uses_mfma(p) || ubf::staged_translate_supported(p)) ? 1 : 0;
   out->precision = p.precision;
   out->n_scatterers = p.n_scat();
   out->translate_groups = p.n_groups();

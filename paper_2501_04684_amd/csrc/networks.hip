@@ -1,4 +1,8 @@
-// Translation by complex-valued fully connected networks (Sec. 3, Fig. 5):
+// Stage 2 with the box vectors staged in LDS: translation by complex-valued
+// fully connected networks (Sec. 3, Fig. 5) and, for box sizes whose
+// columns do not fit in registers, the operator-table product (Eq. 13).
+//
+// Networks:
 // the network of a translation vector w stands in for the product G_w P_i of
 // Eq. 13, and stage 3 is unchanged. For a source box vector x (3N_d complex
 // values) with s = ||x||_inf (largest modulus) the pair's contribution is
@@ -113,6 +117,25 @@ __device__ inline floatx16 mfma4(floatx4 a, floatx4 b, floatx16 acc) {
   return acc;
 }
 
+// The 32 source box vectors of pairs begin + c0 .. begin + c0 + ncol - 1
+// (planar padded, 2*KH floats each) into LDS columns of pitch XP floats;
+// columns past ncol are zero.
+template <int KH, int XP>
+__device__ inline void stage_columns(floatx4* xs4, const float* __restrict__ Pr,
+                                     const int32_t* __restrict__ pair_src, int first,
+                                     int ncol) {
+  constexpr int Q = 2 * KH / 4;  // 16-byte pieces of a box vector
+  for (int i = threadIdx.x; i < 32 * Q; i += kBlock) {
+    const int c = i / Q, q = i - c * Q;
+    floatx4 v = {0.f, 0.f, 0.f, 0.f};
+    if (c < ncol) {
+      const int src = pair_src[first + c];
+      v = reinterpret_cast<const floatx4*>(Pr + (int64_t)src * 2 * KH)[q];
+    }
+    xs4[c * (XP / 4) + q] = v;
+  }
+}
+
 // One workgroup per 32 pairs of a chunk (a chunk holds up to 128 pairs of
 // one offset; blockIdx.x = 4 * chunk + quarter). The 32 source box vectors
 // are staged in LDS; wavefront w computes layer-1 row blocks w, w + 4, ...
@@ -138,7 +161,6 @@ __global__ __launch_bounds__(kBlock, 2) void translate_cvfcnn_kernel(
   constexpr int HPT = 2 * HP + 4;    // LDS pitch of a hidden column
   constexpr int OB = (2 * NU + 31) / 32;
   constexpr int PSTR = 2 * KH;
-  constexpr int Q = 2 * KH / 4;      // 16-byte pieces of a box vector
   __shared__ floatx4 xs4[32 * XP / 4];
   __shared__ floatx4 hs4[32 * HPT / 4];
   float* xs = reinterpret_cast<float*>(xs4);
@@ -156,15 +178,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_cvfcnn_kernel(
   const float* no = net + (size_t)o * NF;
   const float* Pr = P + (int64_t)rhs * n_box * 2 * KH;
 
-  for (int i = t; i < 32 * Q; i += kBlock) {
-    const int c = i / Q, q = i - c * Q;
-    floatx4 v = {0.f, 0.f, 0.f, 0.f};
-    if (c < ncol) {
-      const int src = pair_src[begin + c0 + c];
-      v = reinterpret_cast<const floatx4*>(Pr + (int64_t)src * 2 * KH)[q];
-    }
-    xs4[c * (XP / 4) + q] = v;
-  }
+  stage_columns<KH, XP>(xs4, Pr, pair_src, begin + c0, ncol);
   const bool live = r < ncol;
   const int pos = begin + c0 + min(r, ncol - 1);
   const int src = pair_src[pos];
@@ -236,6 +250,60 @@ __global__ __launch_bounds__(kBlock, 2) void translate_cvfcnn_kernel(
   }
 }
 
+// Operator-table product E = G_w P for box sizes whose columns do not fit
+// in registers (N_u = 192): the scheme of the network kernel's second
+// layer with K = 2 N_u, A rows read from the FP32 table (planes re, im of
+// N_u rows of KH floats per offset) and B from the staged box vectors.
+template <int NU>
+__global__ __launch_bounds__(kBlock, 2) void translate_staged_kernel(
+    const float* __restrict__ table, const int32_t* __restrict__ chunks,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
+    const float* __restrict__ P, float* __restrict__ part, int64_t n_box, int64_t n_pairs) {
+  constexpr int KH = (NU + 3) & ~3;
+  constexpr int XP = 2 * KH + 4;
+  constexpr int OB = (2 * NU + 31) / 32;
+  constexpr int PSTR = 2 * KH;
+  __shared__ floatx4 xs4[32 * XP / 4];
+  const float* xs = reinterpret_cast<const float*>(xs4);
+
+  const int chunk = blockIdx.x >> 2;
+  const int c0 = (blockIdx.x & 3) * 32;
+  const int o = chunks[4 * chunk], begin = chunks[4 * chunk + 1];
+  const int count = chunks[4 * chunk + 2];
+  if (c0 >= count) return;  // whole workgroup
+  const int ncol = min(32, count - c0);
+  const int rhs = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+  stage_columns<KH, XP>(xs4, P + (int64_t)rhs * n_box * 2 * KH, pair_src, begin + c0, ncol);
+  const bool live = r < ncol;
+  const int dst = pair_dst[begin + c0 + min(r, ncol - 1)];
+  __syncthreads();
+  const float* Go = table + (size_t)o * 2 * NU * KH;
+  float* prow = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
+  for (int ob = wave; ob < OB; ob += 4) {
+    const int row = ob * 32 + r;
+    const int opart = (row >= NU && row < 2 * NU) ? 1 : 0;
+    const int u = row < NU ? row : (row < 2 * NU ? row - NU : 0);
+    const int plane = opart == 0 ? h : 1 - h;
+    const float sgn = (opart == 0 && h == 1) ? -1.f : 1.f;
+    const floatx4* arow = reinterpret_cast<const floatx4*>(Go + ((size_t)plane * NU + u) * KH);
+    const floatx4* brow = reinterpret_cast<const floatx4*>(xs + r * XP + h * KH);
+    floatx16 acc = {};
+#pragma unroll 4
+    for (int g = 0; g < KH / 4; ++g) acc = mfma4(arow[g] * sgn, brow[g], acc);
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r0 = ob * 32 + 8 * q + 4 * h;
+        if (r0 < 2 * NU)
+          *reinterpret_cast<floatx4*>(prow + r0) =
+              floatx4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+      }
+    }
+  }
+}
+
 int grid_for(int64_t total) {
   const int64_t g = (total + kBlock - 1) / kBlock;
   return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
@@ -301,8 +369,30 @@ int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs
     default: return (int)hipErrorInvalidValue;  // rejected when the networks are set
   }
 #undef UBF_NET
-#undef UBF_LAUNCH
   return (int)hipGetLastError();
 }
+
+bool staged_translate_supported(const Plan& p) { return !p.split() && p.nu == 192; }
+
+int launch_translate_staged(const Plan& p, const float* P, float* part, int nrhs, void* stream,
+                            const StageEvents* ev) {
+  hipStream_t s = (hipStream_t)stream;
+  const int nch = (int)p.n_chunks();
+  hipEvent_t t0 = ev ? ev->start : nullptr, t1 = ev ? ev->stop : nullptr;
+  if (nch == 0) {
+    if (ev) {
+      hipError_t e = hipEventRecord(t0, s);
+      if (e == hipSuccess) e = hipEventRecord(t1, s);
+      return (int)e;
+    }
+    return 0;
+  }
+  if (p.nu != 192 || p.split()) return (int)hipErrorInvalidValue;
+  UBF_LAUNCH(t0, t1, translate_staged_kernel<192>, dim3((unsigned)(4 * nch), nrhs), s,
+             p.d_table, p.d_chunks, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
+             p.n_pairs());
+  return (int)hipGetLastError();
+}
+#undef UBF_LAUNCH
 
 }  // namespace ubf

@@ -31,4 +31,10 @@ int launch_network_pack(const Plan& p, int hidden, const void* W1, const void* b
 int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs, void* stream,
                             const StageEvents* ev = nullptr);
 
+// Stage 2 by the FP32 operator table with the box vectors staged in LDS,
+// for box sizes whose columns do not fit in registers (N_u = 192).
+bool staged_translate_supported(const Plan& p);
+int launch_translate_staged(const Plan& p, const float* P, float* part, int nrhs, void* stream,
+                            const StageEvents* ev = nullptr);
+
 }  // namespace ubf

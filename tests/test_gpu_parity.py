@@ -132,6 +132,7 @@ def test_stages_separately():
     (1, W.grid_boxes(5, 5, 5)),
     (2, W.grid_boxes(4, 6, 4)),
     (4, W.grid_boxes(4, 4, 4)),
+    (4, W.grid_boxes(4, 4, 5)),
 ])
 def test_other_dipole_grids(n_d, boxes):
     announce("n_d", n_d, len(boxes), "boxes")
@@ -141,6 +142,24 @@ def test_other_dipole_grids(n_d, boxes):
     E = run_translate(ff, P)
     ref = O.translate(P.astype(np.complex128), boxes, 0.25, 2 * np.pi, n_d)
     assert rel_l2(E, ref) <= TOL
+
+
+def test_nd4_sphere_full_size():
+    # 762-box sphere at a = 0.125, n_d = 4 (192 coefficients per box): the
+    # operator-table product with the box vectors staged in LDS, all 22,602
+    # pairs, two right-hand sides
+    w = W.config(6, nrhs=2)
+    announce("n_d=4 sphere", w.name)
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=2)
+    assert ff.info["mfma"] == 1
+    x = w.coefficients()
+    y = to_host(ff(to_dev(x)))
+    ref = O.far_mvm(x.astype(np.complex128), w.boxes, w.a, w.k, w.n_d, mode=w.far_mode)
+    for r in range(2):
+        err = rel_l2(y[r], ref[r])
+        print(f"{w.name} rhs {r}: rel_l2 = {err:.3e}")
+        assert err <= TOL
+    ff.close()
 
 
 def test_full_far_set():

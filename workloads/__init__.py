@@ -235,6 +235,10 @@ def config(idx: int, **over) -> Workload:
        concatenation and ``extra["scatterers"]`` the list of box arrays
        (``count=`` picks another number of scatterers).
 
+    6: the network translation workload of Sec. 3 and Sec. 5: a sphere of
+       diameter 2 wavelengths voxelised at a = 0.125 (its centre-rule shell,
+       radius 1, thickness 0.125), n_d = 4 (3 N_d = 192), ILIST.
+
     The serving stream (Poisson arrivals of solves on random-occupancy
     grids) is ``serving_requests``.
     """
@@ -260,6 +264,9 @@ def config(idx: int, **over) -> Workload:
                      0.25, TWO_PI, 3, "ilist", nrhs=4, seed=4,
                      extra={"scatterers": [b for _, b in parts],
                             "kinds": [k for k, _ in parts]})
+    elif idx == 6:
+        w = Workload("sphere_d2_a0.125_nd4", shell_boxes(1.0, 0.125, 0.125), 0.125,
+                     TWO_PI, 4, "ilist", seed=6)
     else:
         raise ValueError(f"unknown workload {idx}")
     for key, v in over.items():
