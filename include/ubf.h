@@ -237,8 +237,10 @@ int ubf_plan_replay(ubf_plan* plan, void* hip_stream);
  * work chunks), keep the fastest, and write the chosen count to
  * *groups_out (may be NULL). Runs and waits on hip_stream; overwrites the
  * workspace's internal vectors (never x or y). Results of later products
- * do not depend on the choice. Errors: UBF_EINVAL (null plan, nrhs out of
- * 1..max_nrhs, reps out of 1..1000), UBF_ESTATE (unbound), UBF_EDEVICE. */
+ * do not depend on the choice. Plans whose stage 2 has no persistent grid
+ * (networks set, or 192 coefficients per box in FP32) are left as they
+ * are. Errors: UBF_EINVAL (null plan, nrhs out of 1..max_nrhs, reps out of
+ * 1..1000), UBF_ESTATE (unbound), UBF_EDEVICE. */
 int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
                   int32_t* groups_out);
 

@@ -303,6 +303,11 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
   if (nrhs < 1 || nrhs > p.max_nrhs)
     return fail(UBF_EINVAL, "nrhs must be in 1..max_nrhs of the binding");
   if (reps < 1 || reps > 1000) return fail(UBF_EINVAL, "reps must be in 1..1000");
+  if (p.hidden > 0 || ubf::staged_translate_supported(p)) {
+    // stage 2 runs one workgroup per 32 pairs here: no persistent grid to size
+    if (groups_out) *groups_out = (int32_t)p.n_groups();
+    return ok();
+  }
   plan->drop_graph();
   hipStream_t s = (hipStream_t)hip_stream;
   const ubf::Layout L = ubf::workspace_layout(p, p.max_nrhs);

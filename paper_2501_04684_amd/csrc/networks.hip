@@ -35,14 +35,28 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int kBlock = 256;
 static_assert(kChunk == 128, "a chunk is four quarters of 32 pairs");
 
-// Network image of one offset, in floats (all parts 16-byte aligned):
-//   W1 planes (re, im) [2][HP][KH]  rows = hidden units, columns = inputs
-//   b1 (re, im)        [2][HP]
-//   W2 planes (re, im) [2][NU][HP] rows = outputs, columns = hidden units
-//   b2 (re, im)        [2][KH]
-// Entries past the network's width or NU are zero.
+// Network image of one offset, in floats. The weights are stored in the
+// matrix-core fragment order of the kernel below (sign of -W1i / -W2i
+// included), so that a wavefront's 16-byte loads of one group of four
+// k-steps are 1 KB contiguous:
+//   W1 fragments [2 HB row blocks][KH/4 groups][64 lanes][4]: row block rb of
+//     [[W1r, -W1i], [W1i, W1r]] (rows: real then imaginary hidden units, HP
+//     each), lane l = row l % 32 of the block and input half l / 32
+//   b1 (re, im)  [2][HP]
+//   W2 fragments [OB row blocks][HP/4 groups][64 lanes][4]: row block ob of
+//     [[W2r, -W2i], [W2i, W2r]] (rows: Er then Ei, N_u each), lane l = row
+//     l % 32 and hidden half l / 32
+//   b2 (re, im)  [2][KH]
+// Entries past the network's width, N_u or 2 N_u rows are zero.
 __host__ __device__ constexpr int64_t image_floats(int nu, int kh, int hp) {
-  return 2LL * hp * kh + 2LL * hp + 2LL * nu * hp + 2LL * kh;
+  return (2LL * hp / 32) * (kh / 4) * 256 + 2LL * hp +
+         (int64_t)((2 * nu + 31) / 32) * (hp / 4) * 256 + 2LL * kh;
+}
+
+// Value of the real form [[Xr, -Xi], [Xi, Xr]] at a row of the real
+// (im_row false) or imaginary part and column half h, from the entry c.
+__device__ inline float real_form(float2 c, bool im_row, int h) {
+  return !im_row ? (h == 0 ? c.x : -c.y) : (h == 0 ? c.y : c.x);
 }
 
 // Caller layout (complex64, offsets in plan order): W1 [n_off][H][NU],
@@ -52,19 +66,22 @@ __global__ __launch_bounds__(kBlock) void network_pack_kernel(
     const float2* __restrict__ W2, const float2* __restrict__ b2, float* __restrict__ img,
     int64_t n_off, int nu, int kh, int hp, int hidden) {
   const int64_t nf = image_floats(nu, kh, hp);
-  const int64_t w1 = 2LL * hp * kh, bb1 = 2LL * hp, w2 = 2LL * nu * hp;
+  const int g1 = kh / 4, g2 = hp / 4, hb = hp / 32;
+  const int64_t w1 = (int64_t)(2 * hb) * g1 * 256, bb1 = 2LL * hp;
+  const int64_t w2 = (int64_t)((2 * nu + 31) / 32) * g2 * 256;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_off * nf;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t o = t / nf;
     int64_t i = t - o * nf;
     float v = 0.f;
     if (i < w1) {
-      const int64_t plane = i / ((int64_t)hp * kh), rem = i % ((int64_t)hp * kh);
-      const int64_t m = rem / kh, k = rem % kh;
-      if (m < hidden && k < nu) {
-        const float2 c = W1[(o * hidden + m) * nu + k];
-        v = plane ? c.y : c.x;
-      }
+      const int j = (int)(i & 3), l = (int)((i >> 2) & 63);
+      const int64_t bg = i >> 8;
+      const int g = (int)(bg % g1), rb = (int)(bg / g1);
+      const int row = rb * 32 + (l & 31), h = l >> 5, k = 4 * g + j;
+      const bool im_row = row >= hp;
+      const int m = im_row ? row - hp : row;
+      if (m < hidden && k < nu) v = real_form(W1[(o * hidden + m) * nu + k], im_row, h);
     } else if ((i -= w1) < bb1) {
       const int64_t plane = i / hp, m = i % hp;
       if (m < hidden) {
@@ -72,11 +89,14 @@ __global__ __launch_bounds__(kBlock) void network_pack_kernel(
         v = plane ? c.y : c.x;
       }
     } else if ((i -= bb1) < w2) {
-      const int64_t plane = i / ((int64_t)nu * hp), rem = i % ((int64_t)nu * hp);
-      const int64_t u = rem / hp, m = rem % hp;
-      if (m < hidden) {
-        const float2 c = W2[(o * nu + u) * hidden + m];
-        v = plane ? c.y : c.x;
+      const int j = (int)(i & 3), l = (int)((i >> 2) & 63);
+      const int64_t bg = i >> 8;
+      const int g = (int)(bg % g2), ob = (int)(bg / g2);
+      const int row = ob * 32 + (l & 31), h = l >> 5, m = 4 * g + j;
+      if (row < 2 * nu && m < hidden) {
+        const bool im_row = row >= nu;
+        const int u = im_row ? row - nu : row;
+        v = real_form(W2[(o * nu + u) * hidden + m], im_row, h);
       }
     } else {
       i -= w2;
@@ -109,13 +129,33 @@ __global__ __launch_bounds__(kBlock) void linf_kernel(const float* __restrict__ 
   if (l == 0) out[row] = m;
 }
 
-__device__ inline floatx16 mfma4(floatx4 a, floatx4 b, floatx16 acc) {
-  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
-  return acc;
+// acc[i] += A_i B for the PER row blocks a wavefront owns, over G groups of
+// four k-steps: per group one 16-byte A load per block and lane (fragment
+// order: arow[i] points at the lane's piece of group 0, the next group is
+// 64 pieces on) and one 16-byte B load from LDS shared by all blocks;
+// consecutive MFMAs go to different blocks' accumulators.
+template <int PER, int G>
+__device__ inline void rowblock_products(floatx16 (&acc)[PER], const floatx4* const (&arow)[PER],
+                                         const floatx4* brow) {
+#pragma unroll 2
+  for (int g = 0; g < G; ++g) {
+    const floatx4 b = brow[g];
+    floatx4 a[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) a[i] = arow[i][g * 64];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int i = 0; i < PER; ++i)
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[kk], acc[i], 0, 0, 0);
+  }
 }
+
+// Work item of this workgroup: consecutive items (the quarters of a chunk,
+// then the chunks of an offset, which share their weights) go to the same
+// XCD, whose L2 then fetches those weights once. The hardware deals
+// workgroups to the 8 XCDs round robin; the grid is a multiple of 8.
+__device__ inline int xcd_item(int bid, int grid) { return (bid & 7) * (grid >> 3) + (bid >> 3); }
 
 // The 32 source box vectors of pairs begin + c0 .. begin + c0 + ncol - 1
 // (planar padded, 2*KH floats each) into LDS columns of pitch XP floats;
@@ -137,37 +177,40 @@ __device__ inline void stage_columns(floatx4* xs4, const float* __restrict__ Pr,
 }
 
 // One workgroup per 32 pairs of a chunk (a chunk holds up to 128 pairs of
-// one offset; blockIdx.x = 4 * chunk + quarter). The 32 source box vectors
-// are staged in LDS; wavefront w computes layer-1 row blocks w, w + 4, ...
-// (the A values of its lane's row are read from the network image, four
-// k-steps per 16-byte load, with the sign of -W1i applied on load), writes
-// bias + CReLU to the hidden tile, and after a barrier computes layer-2 row
-// blocks w, w + 4, ... the same way. Lane l owns pair column l % 32; its
-// 4-row pieces of each output block go to the pair's partial row, whose
-// positions are the output rows [Er | Ei].
+// one offset; work item 4 * chunk + quarter, XCD-aware), three per CU. The 32
+// source box vectors are staged in LDS; wavefront w computes layer-1 row
+// blocks w, w + 4, ... (A from the network image in fragment order, B from
+// LDS); after a barrier it writes bias + CReLU into the hidden tile, which
+// reuses the staged vectors' LDS, and after another barrier computes
+// layer-2 row blocks w, w + 4, ... the same way. Lane l owns pair column
+// l % 32; its 4-row pieces of each output block go to the pair's partial
+// row, whose positions are the output rows [Er | Ei].
 template <int NU, int HB>
-__global__ __launch_bounds__(kBlock, 2) void translate_cvfcnn_kernel(
+__global__ __launch_bounds__(kBlock, 3) void translate_cvfcnn_kernel(
     const float* __restrict__ net, const int32_t* __restrict__ chunks,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
     const float* __restrict__ P, const float* __restrict__ linf, float* __restrict__ part,
-    int64_t n_box, int64_t n_pairs, int hidden) {
+    int64_t n_box, int64_t n_pairs, int hidden, int n_chunks) {
   constexpr int KH = (NU + 3) & ~3;
   constexpr int HP = 32 * HB;
   constexpr int64_t NF = image_floats(NU, KH, HP);
-  constexpr int B1_OFF = 2 * HP * KH;
+  constexpr int B1_OFF = 2 * HB * (KH / 4) * 256;
   constexpr int W2_OFF = B1_OFF + 2 * HP;
-  constexpr int B2_OFF = W2_OFF + 2 * NU * HP;
+  constexpr int B2_OFF = W2_OFF + ((2 * NU + 31) / 32) * (HP / 4) * 256;
   constexpr int XP = 2 * KH + 4;     // LDS pitch of a staged box vector
   constexpr int HPT = 2 * HP + 4;    // LDS pitch of a hidden column
   constexpr int OB = (2 * NU + 31) / 32;
   constexpr int PSTR = 2 * KH;
-  __shared__ floatx4 xs4[32 * XP / 4];
-  __shared__ floatx4 hs4[32 * HPT / 4];
+  // the hidden tile reuses the staged vectors' LDS once layer 1 has read them
+  constexpr int TILE = 32 * (XP > HPT ? XP : HPT);
+  __shared__ floatx4 xs4[TILE / 4];
   float* xs = reinterpret_cast<float*>(xs4);
-  float* hs = reinterpret_cast<float*>(hs4);
+  float* hs = xs;
 
-  const int chunk = blockIdx.x >> 2;
-  const int c0 = (blockIdx.x & 3) * 32;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= 4 * n_chunks) return;  // grid padding
+  const int chunk = item >> 2;
+  const int c0 = (item & 3) * 32;
   const int o = chunks[4 * chunk], begin = chunks[4 * chunk + 1];
   const int count = chunks[4 * chunk + 2];
   if (c0 >= count) return;  // whole workgroup
@@ -187,63 +230,78 @@ __global__ __launch_bounds__(kBlock, 2) void translate_cvfcnn_kernel(
   const float inv_s = s > 0.f ? 1.f / s : 0.f;
   __syncthreads();
 
-  // layer 1: A row = hidden unit m of part (0: real, 1: imaginary);
-  // lane half h multiplies the real (h = 0) or imaginary (h = 1) inputs
-  for (int rb = wave; rb < 2 * HB; rb += 4) {
-    const int hpart = rb / HB;
-    const int m0 = (rb % HB) * 32;
-    const int plane = hpart == 0 ? h : 1 - h;
-    const float sgn = (hpart == 0 && h == 1) ? -1.f : 1.f;
-    const floatx4* arow =
-        reinterpret_cast<const floatx4*>(no + ((size_t)plane * HP + m0 + r) * KH);
-    const floatx4* brow = reinterpret_cast<const floatx4*>(xs + r * XP + h * KH);
-    floatx16 acc = {};
-#pragma unroll 4
-    for (int g = 0; g < KH / 4; ++g) acc = mfma4(arow[g] * sgn, brow[g], acc);
-    const float* b1 = no + B1_OFF + hpart * HP + m0;
+  // layer 1: A row = hidden unit m of part (0: real, 1: imaginary); lane
+  // half h multiplies the real (h = 0) or imaginary (h = 1) inputs. Row
+  // block rb = wave + 4 i (i < PER1); blocks past 2 HB are computed on
+  // block 0's rows and dropped.
+  {
+    constexpr int NB = 2 * HB, PER1 = (NB + 3) / 4;
+    floatx16 acc[PER1];
+    const floatx4* arow[PER1];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      floatx4 v;
+    for (int i = 0; i < PER1; ++i) {
+      const int rb = min(wave + 4 * i, NB - 1);
+      arow[i] = reinterpret_cast<const floatx4*>(no) + (size_t)rb * (KH / 4) * 64 + lane;
+      acc[i] = floatx16{};
+    }
+    if (wave < NB)  // wave-uniform
+      rowblock_products<PER1, KH / 4>(acc, arow,
+                                      reinterpret_cast<const floatx4*>(xs + r * XP + h * KH));
+    __syncthreads();  // every wavefront is done with the staged vectors
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int row = 8 * q + 4 * h + jj;
-        const float z = fmaf(acc[4 * q + jj], inv_s, b1[row]);
-        v[jj] = (m0 + row < hidden) ? fmaxf(z, 0.f) : 0.f;
+    for (int i = 0; i < PER1; ++i) {
+      const int rb = wave + 4 * i;
+      if (rb >= NB) continue;
+      const int hpart = rb / HB, m0 = (rb % HB) * 32;
+      const float* b1 = no + B1_OFF + hpart * HP + m0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        floatx4 v;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int row = 8 * q + 4 * h + jj;
+          const float z = fmaf(acc[i][4 * q + jj], inv_s, b1[row]);
+          v[jj] = (m0 + row < hidden) ? fmaxf(z, 0.f) : 0.f;
+        }
+        *reinterpret_cast<floatx4*>(hs + r * HPT + rb * 32 + 8 * q + 4 * h) = v;
       }
-      *reinterpret_cast<floatx4*>(hs + r * HPT + rb * 32 + 8 * q + 4 * h) = v;
     }
   }
   __syncthreads();
 
-  // layer 2: A row = output row of [Er | Ei]; padding rows (>= 2 NU) read
-  // row 0 and are not stored
+  // layer 2: A row = output row of [Er | Ei]; row blocks ob = wave + 4 i
   float* prow = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
-  for (int ob = wave; ob < OB; ob += 4) {
-    const int row = ob * 32 + r;
-    const int opart = (row >= NU && row < 2 * NU) ? 1 : 0;
-    const int u = row < NU ? row : (row < 2 * NU ? row - NU : 0);
-    const int plane = opart == 0 ? h : 1 - h;
-    const float sgn = (opart == 0 && h == 1) ? -1.f : 1.f;
-    const floatx4* arow =
-        reinterpret_cast<const floatx4*>(no + W2_OFF + ((size_t)plane * NU + u) * HP);
-    const floatx4* brow = reinterpret_cast<const floatx4*>(hs + r * HPT + h * HP);
-    floatx16 acc = {};
-#pragma unroll 4
-    for (int g = 0; g < HP / 4; ++g) acc = mfma4(arow[g] * sgn, brow[g], acc);
+  {
+    constexpr int PER = (OB + 3) / 4;
+    floatx16 acc[PER];
+    const floatx4* arow[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int ob = min(wave + 4 * i, OB - 1);
+      arow[i] = reinterpret_cast<const floatx4*>(no + W2_OFF) + (size_t)ob * (HP / 4) * 64 + lane;
+      acc[i] = floatx16{};
+    }
+    rowblock_products<PER, HP / 4>(acc, arow,
+                                   reinterpret_cast<const floatx4*>(hs + r * HPT + h * HP));
     if (live) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r0 = ob * 32 + 8 * q + 4 * h;  // first of this lane's 4 rows
-        if (r0 < 2 * NU) {
-          floatx4 v;
+      for (int i = 0; i < PER; ++i) {
+        const int ob = wave + 4 * i;
+        if (ob >= OB) continue;
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            const int orow = r0 + jj;
-            const float b = orow < NU ? no[B2_OFF + orow]
-                                      : (orow < 2 * NU ? no[B2_OFF + KH + orow - NU] : 0.f);
-            v[jj] = s * (acc[4 * q + jj] + b);
+        for (int q = 0; q < 4; ++q) {
+          const int r0 = ob * 32 + 8 * q + 4 * h;  // first of this lane's 4 rows
+          if (r0 < 2 * NU) {
+            floatx4 v;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              const int orow = r0 + jj;
+              const float b = orow < NU ? no[B2_OFF + orow]
+                                        : (orow < 2 * NU ? no[B2_OFF + KH + orow - NU] : 0.f);
+              v[jj] = s * (acc[i][4 * q + jj] + b);
+            }
+            *reinterpret_cast<floatx4*>(prow + r0) = v;
           }
-          *reinterpret_cast<floatx4*>(prow + r0) = v;
         }
       }
     }
@@ -252,13 +310,15 @@ __global__ __launch_bounds__(kBlock, 2) void translate_cvfcnn_kernel(
 
 // Operator-table product E = G_w P for box sizes whose columns do not fit
 // in registers (N_u = 192): the scheme of the network kernel's second
-// layer with K = 2 N_u, A rows read from the FP32 table (planes re, im of
-// N_u rows of KH floats per offset) and B from the staged box vectors.
+// layer with K = 2 N_u, A read from the FP32 table in fragment order (per
+// offset: 2 N_u / 32 row blocks of [[Gr, -Gi], [Gi, Gr]], KH/4 groups, 64
+// lanes x 4 floats) and B from the staged box vectors.
 template <int NU>
 __global__ __launch_bounds__(kBlock, 2) void translate_staged_kernel(
     const float* __restrict__ table, const int32_t* __restrict__ chunks,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
-    const float* __restrict__ P, float* __restrict__ part, int64_t n_box, int64_t n_pairs) {
+    const float* __restrict__ P, float* __restrict__ part, int64_t n_box, int64_t n_pairs,
+    int n_chunks) {
   constexpr int KH = (NU + 3) & ~3;
   constexpr int XP = 2 * KH + 4;
   constexpr int OB = (2 * NU + 31) / 32;
@@ -266,8 +326,10 @@ __global__ __launch_bounds__(kBlock, 2) void translate_staged_kernel(
   __shared__ floatx4 xs4[32 * XP / 4];
   const float* xs = reinterpret_cast<const float*>(xs4);
 
-  const int chunk = blockIdx.x >> 2;
-  const int c0 = (blockIdx.x & 3) * 32;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= 4 * n_chunks) return;  // grid padding
+  const int chunk = item >> 2;
+  const int c0 = (item & 3) * 32;
   const int o = chunks[4 * chunk], begin = chunks[4 * chunk + 1];
   const int count = chunks[4 * chunk + 2];
   if (c0 >= count) return;  // whole workgroup
@@ -279,26 +341,29 @@ __global__ __launch_bounds__(kBlock, 2) void translate_staged_kernel(
   const bool live = r < ncol;
   const int dst = pair_dst[begin + c0 + min(r, ncol - 1)];
   __syncthreads();
-  const float* Go = table + (size_t)o * 2 * NU * KH;
+  const floatx4* Go = reinterpret_cast<const floatx4*>(table) + (size_t)o * OB * (KH / 4) * 64;
   float* prow = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
-  for (int ob = wave; ob < OB; ob += 4) {
-    const int row = ob * 32 + r;
-    const int opart = (row >= NU && row < 2 * NU) ? 1 : 0;
-    const int u = row < NU ? row : (row < 2 * NU ? row - NU : 0);
-    const int plane = opart == 0 ? h : 1 - h;
-    const float sgn = (opart == 0 && h == 1) ? -1.f : 1.f;
-    const floatx4* arow = reinterpret_cast<const floatx4*>(Go + ((size_t)plane * NU + u) * KH);
-    const floatx4* brow = reinterpret_cast<const floatx4*>(xs + r * XP + h * KH);
-    floatx16 acc = {};
-#pragma unroll 4
-    for (int g = 0; g < KH / 4; ++g) acc = mfma4(arow[g] * sgn, brow[g], acc);
-    if (live) {
+  constexpr int PER = (OB + 3) / 4;
+  floatx16 acc[PER];
+  const floatx4* arow[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    arow[i] = Go + (size_t)min(wave + 4 * i, OB - 1) * (KH / 4) * 64 + lane;
+    acc[i] = floatx16{};
+  }
+  rowblock_products<PER, KH / 4>(acc, arow,
+                                 reinterpret_cast<const floatx4*>(xs + r * XP + h * KH));
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int ob = wave + 4 * i;
+      if (ob >= OB) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r0 = ob * 32 + 8 * q + 4 * h;
         if (r0 < 2 * NU)
           *reinterpret_cast<floatx4*>(prow + r0) =
-              floatx4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+              floatx4{acc[i][4 * q], acc[i][4 * q + 1], acc[i][4 * q + 2], acc[i][4 * q + 3]};
       }
     }
   }
@@ -355,12 +420,12 @@ int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs
              rows, p.nu, p.kh);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nch == 0) return (int)e;
-  const dim3 grid((unsigned)(4 * nch), nrhs);
+  const dim3 grid((unsigned)((4 * nch + 7) / 8 * 8), nrhs);
   hipEvent_t none = nullptr;
 #define UBF_NET(NU, HB)                                                                    \
   UBF_LAUNCH(none, t1, (translate_cvfcnn_kernel<NU, HB>), grid, s, p.d_net, p.d_chunks,    \
              p.d_pair_src, p.d_pair_dst, P, p.d_box_scale, part, p.n_box, p.n_pairs(),     \
-             p.hidden)
+             p.hidden, nch)
   const bool wide = p.hidden > 32;
   switch (p.nu) {
     case 24: if (wide) UBF_NET(24, 2); else UBF_NET(24, 1); break;
@@ -388,9 +453,9 @@ int launch_translate_staged(const Plan& p, const float* P, float* part, int nrhs
     return 0;
   }
   if (p.nu != 192 || p.split()) return (int)hipErrorInvalidValue;
-  UBF_LAUNCH(t0, t1, translate_staged_kernel<192>, dim3((unsigned)(4 * nch), nrhs), s,
-             p.d_table, p.d_chunks, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
-             p.n_pairs());
+  UBF_LAUNCH(t0, t1, translate_staged_kernel<192>, dim3((unsigned)((4 * nch + 7) / 8 * 8), nrhs),
+             s, p.d_table, p.d_chunks, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
+             p.n_pairs(), nch);
   return (int)hipGetLastError();
 }
 #undef UBF_LAUNCH

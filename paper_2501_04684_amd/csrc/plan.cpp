@@ -110,6 +110,28 @@ void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<doub
       }
     return;
   }
+  if (P.staged()) {
+    // block b, group g, lane l (row r = l % 32 of the block, K half h = l / 32:
+    // the real inputs for h = 0, the imaginary ones for h = 1), k-steps
+    // 4g..4g+3: Er rows take (Gr, -Gi), Ei rows (Gi, Gr); rows past 2 N_u and
+    // columns past N_u are zero
+    const int g4 = P.kh / 4, nb = (2 * P.nu + 31) / 32;
+    float* f = (float*)dst;
+    for (int b = 0; b < nb; ++b)
+      for (int g = 0; g < g4; ++g)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 4; ++j) {
+            const int row = 32 * b + (l & 31), h = l >> 5, k = 4 * g + j;
+            double v = 0.0;
+            if (row < 2 * P.nu && k < P.nu) {
+              const bool ei = row >= P.nu;
+              const std::complex<double> c = G[(size_t)(ei ? row - P.nu : row) * P.nu + k];
+              v = !ei ? (h == 0 ? c.real() : -c.imag()) : (h == 0 ? c.imag() : c.real());
+            }
+            f[(((size_t)b * g4 + g) * 64 + l) * 4 + j] = (float)v;
+          }
+    return;
+  }
   if (!P.split()) {
     const size_t plane = P.plane_floats();
     float* re = (float*)dst;
@@ -478,8 +500,9 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   P.n_orbits = (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
 
   // Operator table image, one offset at a time (cached across plans).
-  const size_t img_bytes = P.split() ? (size_t)4 * P.nu * P.khb * sizeof(uint16_t)
-                                     : (size_t)2 * P.nu * P.kh * sizeof(float);
+  const size_t img_bytes = P.split()    ? (size_t)4 * P.nu * P.khb * sizeof(uint16_t)
+                           : P.staged() ? P.staged_op_floats() * sizeof(float)
+                                        : (size_t)2 * P.nu * P.kh * sizeof(float);
   if (P.split())
     P.table_bf16.assign((size_t)n_off * img_bytes / sizeof(uint16_t), 0);
   else

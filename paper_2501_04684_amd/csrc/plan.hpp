@@ -141,6 +141,12 @@ struct Plan {
   int32_t n_scat() const { return (int32_t)scat_ptr.size() - 1; }
   size_t plane_floats() const { return (size_t)nu * kh; }
   size_t op_floats() const { return 2 * plane_floats(); }
+  // FP32 operators of boxes whose columns do not fit in registers
+  // (N_u = 192) are stored in the matrix-core fragment order of the staged
+  // kernel: per 32-row block of [[Gr, -Gi], [Gi, Gr]], per group of four
+  // k-steps, 64 lanes x 4 floats.
+  bool staged() const { return !split() && nu == 192; }
+  size_t staged_op_floats() const { return (size_t)((2 * nu + 31) / 32) * (kh / 4) * 256; }
   int pstride() const { return 2 * kh; }              // partial rows, floats
   // Box vectors of stage 1 -> 2, in floats: FP32 [re | im] halves, or in
   // split mode [re: hi, lo | im: hi, lo] BF16 runs of khb values.
