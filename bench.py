@@ -586,7 +586,6 @@ def bench_batch(args, U, W, torch):
 
 def bench_serve(args, U, W, torch):
     import numpy as np
-    import oracle as O
     import paper_2501_04684_amd.serve as S
 
     tol, restart, max_steps = 1e-4, 30, 300
@@ -665,6 +664,7 @@ def bench_serve(args, U, W, torch):
                      "frac": ach / peak, "traffic": None},
     }
     if not args.no_cpu_baseline:
+        import oracle as O
         # the oracle's product on whole requests (smallest first), scaled to
         # the stream's products by far-pair count
         by = {r.rid: r for r in ok}
