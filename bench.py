@@ -71,7 +71,7 @@ def issued_16bit_flops(form, nu, n_pairs, nrhs):
 STAGE_KERNELS = {"aggregate": "aggregate_kernel",
                  "translate_mfma": "translate_mfma_kernel",
                  "translate_split": "translate_split_kernel",
-                 "disaggregate": "disaggregate_"}  # the plain or the pipelined kernel
+                 "disaggregate": "disaggregate_"}  # the per-box or the per-wavefront kernel
 
 
 def source_hash(path=KERNEL_SOURCE):

@@ -957,155 +957,92 @@ __global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
   }
 }
 
-// Stage 3 of the whole product when T_j = S_j^T and E_j comes from the
-// partial rows: a persistent pipeline over boxes. Each workgroup walks the
-// boxes blockIdx.x, + gridDim.x, ...; for box b it sums b's partial rows
-// (already in registers), stages b's first batch of S_b columns into LDS
-// (already in registers), then issues the loads of the next box into the
-// same registers and applies b while they are in flight. Columns beyond
-// the first batch are streamed afterwards (rare). Same arithmetic and
-// summation order as disaggregate_kernel.
-template <int EQ>
-__global__ __launch_bounds__(kBlock, 2) void disaggregate_pipe_kernel(
+// Stage 3 with one wavefront per box (E_j from the partial rows, N_u <= 84;
+// T_j = S_j^T, or y_j = E_j with IDENT): no workgroup barriers on the box's
+// path. Lane l < R4
+// sums float4 l of the box's partial rows (several rows in flight); the sums
+// go to the wavefront's own LDS slot (672 bytes) and come back as this
+// lane's rows of E_j; then 16 columns of S_j per pass, four lanes per column
+// (lane group q takes rows q, q + 4, ...), read from global memory and
+// reduced across the four lanes by shuffles. Same arithmetic as
+// disaggregate_kernel except the order of the partial-row sum.
+template <int EQ, bool IDENT>
+__global__ __launch_bounds__(kBlock) void disaggregate_wave_kernel(
     const float* __restrict__ part, const int32_t* __restrict__ test_ptr, int64_t n_pairs,
-    const int64_t* __restrict__ nb_ptr, const float2* __restrict__ S,
-    float2* __restrict__ y, int64_t n_box, int64_t nb_total, int nu, int kh) {
-  constexpr int LD = ((kStage + 1) / 2 + kBlock - 1) / kBlock;
-  constexpr int PU = 8;
-  __shared__ float4 Es4[98];
-  __shared__ float4 stage4[(kStage + 1) / 2];  // S batch, or the row-sum scratch
-  const float* Es = reinterpret_cast<const float*>(Es4);
-  const float2* stage = reinterpret_cast<const float2*>(stage4);
-  floatx4* stagev = reinterpret_cast<floatx4*>(stage4);
+    const int64_t* __restrict__ nb_ptr, const float2* __restrict__ S, float2* __restrict__ y,
+    int64_t n_box, int64_t nb_total, int nu, int kh) {
+  constexpr int RU = 16;  // partial rows in flight per lane
+  __shared__ float4 Es4[kBlock / 64][42];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+  if (j >= n_box) return;  // whole wavefronts; no barriers below
   const int r = blockIdx.y;
-  const int t = threadIdx.x;
-  float2* yb = y + (int64_t)r * nb_total;
-  const int CB = (kStage - 2) / nu;
-  const int R4 = kh / 2, H = kBlock / R4, g = t % R4, h = t / R4;
+  const int R4 = kh / 2;  // float4 per partial row (<= 42)
+  const int p0 = test_ptr[j], p1 = test_ptr[j + 1];
   const float4* pr = reinterpret_cast<const float4*>(part) + (int64_t)r * n_pairs * R4;
-  const int q = (t & 63) >> 4;
-
-  // the box whose loads are in flight, and the loads themselves
-  int64_t start = 0, nb = 0;
-  int p0 = 0, p1 = 0, shift = 0, lim = 0, n4 = 0, lo = 0, hi = 0;
-  floatx4 tmp[LD];
-  float2 edge0 = make_float2(0.f, 0.f), edge1 = make_float2(0.f, 0.f);
-  float4 pv[PU];
-  auto issue = [&](int64_t b) {
-    start = nb_ptr[b];
-    nb = nb_ptr[b + 1] - start;
-    p0 = test_ptr[b];
-    p1 = test_ptr[b + 1];
-    if (nb > 0) {  // uniform
-      const int ncol = (int)min((int64_t)CB, nb);
-      const float2* blk = S + start * nu;
-      shift = (reinterpret_cast<uintptr_t>(blk) & 15) ? 1 : 0;
-      lim = ncol * nu + shift;
-      n4 = (lim + 1) / 2;
-      lo = shift;
-      hi = (lim & 1) ? n4 - 2 : n4 - 1;
-      const float2* s2 = blk - shift;
-      const floatx4* s4 = reinterpret_cast<const floatx4*>(s2);
+  if (lane < R4) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int p = p0; p < p1; p += RU) {
+      float4 v[RU];
 #pragma unroll
-      for (int it = 0; it < LD; ++it) tmp[it] = s4[min(max(t + it * kBlock, lo), hi)];
-      edge0 = s2[shift ? 1 : 2 * lo];
-      edge1 = s2[(lim & 1) ? 2 * (n4 - 1) : 2 * hi];
-      if (h < H && p1 > p0) {
+      for (int i = 0; i < RU; ++i) v[i] = load_once(&pr[(int64_t)min(p + i, p1 - 1) * R4 + lane]);
 #pragma unroll
-        for (int i = 0; i < PU; ++i) pv[i] = load_once(&pr[(int64_t)min(p0 + h + i * H, p1 - 1) * R4 + g]);
-      }
-    }
-  };
-
-  int64_t b = blockIdx.x;
-  if (b >= n_box) return;
-  issue(b);
-  for (; b < n_box; b += gridDim.x) {
-    const int64_t cstart = start, cnb = nb;
-    const int cp0 = p0, cp1 = p1, cshift = shift, clim = lim, cn4 = n4, clo = lo, chi = hi;
-    __syncthreads();  // the previous box is done with the LDS
-    if (cnb > 0) {
-      // E_b: this box's partial rows, first PU per row group from registers
-      float4* scratch = stage4;
-      if (h < H) {
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (cp1 > cp0) {
-#pragma unroll
-          for (int i = 0; i < PU; ++i)
-            if (cp0 + h + i * H < cp1) {
-              acc.x += pv[i].x;
-              acc.y += pv[i].y;
-              acc.z += pv[i].z;
-              acc.w += pv[i].w;
-            }
+      for (int i = 0; i < RU; ++i)
+        if (p + i < p1) {
+          acc.x += v[i].x;
+          acc.y += v[i].y;
+          acc.z += v[i].z;
+          acc.w += v[i].w;
         }
-#pragma unroll 4
-        for (int p = cp0 + h + PU * H; p < cp1; p += H) {
-          const float4 v = load_once(&pr[(int64_t)p * R4 + g]);
-          acc.x += v.x;
-          acc.y += v.y;
-          acc.z += v.z;
-          acc.w += v.w;
-        }
-        scratch[h * R4 + g] = acc;
-      }
-      __syncthreads();
-      for (int m4 = t; m4 < R4; m4 += kBlock) {
-        float4 s4 = scratch[m4];
-        for (int hh = 1; hh < H; ++hh) {
-          const float4 v = scratch[hh * R4 + m4];
-          s4.x += v.x;
-          s4.y += v.y;
-          s4.z += v.z;
-          s4.w += v.w;
-        }
-        Es4[m4] = s4;
-      }
-      __syncthreads();
-      // S_b's first batch into LDS
+    }
+    if (IDENT) {  // y_j = E_j: this lane's four positions of [Er | Ei]
+      float2* yj = y + (int64_t)r * nb_total + j * nu;
+      const float a4[4] = {acc.x, acc.y, acc.z, acc.w};
 #pragma unroll
-      for (int it = 0; it < LD; ++it) {
-        const int i = t + it * kBlock;
-        if (i >= clo && i <= chi) stagev[i] = tmp[it];
+      for (int k = 0; k < 4; ++k) {
+        const int pos = 4 * lane + k;
+        if (pos < nu) yj[pos].x = a4[k];
+        else if (pos < 2 * nu) yj[pos - nu].y = a4[k];
       }
-      if (t == 0 && cshift) stagev[0] = floatx4{0.f, 0.f, edge0.x, edge0.y};
-      if (t == 1 && (clim & 1)) stagev[cn4 - 1] = floatx4{edge1.x, edge1.y, 0.f, 0.f};
+    } else {
+      Es4[wave][lane] = acc;
     }
-    float er[EQ], ei[EQ];
+  }
+  if (IDENT) return;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const float* Es = reinterpret_cast<const float*>(Es4[wave]);
+  const int q = lane >> 4;
+  float er[EQ], ei[EQ];
 #pragma unroll
-    for (int i = 0; i < EQ; ++i) {
-      const int u = min(q + 4 * i, nu - 1);
-      er[i] = Es[u];
-      ei[i] = Es[nu + u];
-    }
-    // the next box's loads go out before this box is applied
-    if (b + gridDim.x < n_box) issue(b + gridDim.x);
-    __syncthreads();
-    if (cnb <= 0) continue;
-    const int ncol = (int)min((int64_t)CB, cnb);
-    apply_staged<EQ>(stage, cshift, ncol, er, ei, nu, yb + cstart);
-    for (int64_t c0 = CB; c0 < cnb; c0 += CB) {  // more than CB functions (rare)
-      __syncthreads();
-      const int nc = (int)min((int64_t)CB, cnb - c0);
-      const float2* blk = S + (cstart + c0) * nu;
-      const int sh = (reinterpret_cast<uintptr_t>(blk) & 15) ? 1 : 0;
-      const int lm = nc * nu + sh;
-      const int m4n = (lm + 1) / 2;
-      const int l0 = sh, h0 = (lm & 1) ? m4n - 2 : m4n - 1;
-      const float2* s2 = blk - sh;
-      const floatx4* s4 = reinterpret_cast<const floatx4*>(s2);
-      for (int i = l0 + t; i <= h0; i += kBlock) stagev[i] = s4[i];
-      if (t == 0 && sh) {
-        const float2 v = s2[1];
-        stagev[0] = floatx4{0.f, 0.f, v.x, v.y};
+  for (int i = 0; i < EQ; ++i) {
+    const int u = min(q + 4 * i, nu - 1);
+    er[i] = Es[u];
+    ei[i] = Es[nu + u];
+  }
+  const int64_t start = nb_ptr[j];
+  const int64_t nb = nb_ptr[j + 1] - start;
+  const float2* Sb = S + start * nu;
+  float2* yb = y + (int64_t)r * nb_total + start;
+#pragma unroll 2
+  for (int64_t c0 = 0; c0 < nb; c0 += 16) {
+    const int64_t c = c0 + (lane & 15);
+    const float2* col = Sb + min(c, nb - 1) * nu;
+    float2 sv[EQ];
+#pragma unroll
+    for (int i = 0; i < EQ; ++i) sv[i] = col[min(q + 4 * i, nu - 1)];
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int i = 0; i < EQ; ++i)
+      if (q + 4 * i < nu) {
+        sr = fmaf(sv[i].x, er[i], fmaf(-sv[i].y, ei[i], sr));
+        si = fmaf(sv[i].x, ei[i], fmaf(sv[i].y, er[i], si));
       }
-      if (t == 1 && (lm & 1)) {
-        const float2 v = s2[2 * (m4n - 1)];
-        stagev[m4n - 1] = floatx4{v.x, v.y, 0.f, 0.f};
-      }
-      __syncthreads();
-      apply_staged<EQ>(stage, sh, nc, er, ei, nu, yb + cstart + c0);
-    }
+    sr += __shfl_xor(sr, 16, 64);
+    si += __shfl_xor(si, 16, 64);
+    sr += __shfl_xor(sr, 32, 64);
+    si += __shfl_xor(si, 32, 64);
+    if (c < nb && q == 0) yb[c] = make_float2(sr, si);
   }
 }
 
@@ -1235,14 +1172,20 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
              p.d_test_ptr, p.n_pairs(), (const float2*)E, p.d_nb_ptr,                 \
              (const float2*)p.d_S, (const float2*)p.d_T, mode, (float2*)y, p.n_box,    \
              nb_total, p.nu, p.kh)
-  // The pipeline pays off while a box's partial rows are few (interaction
-  // lists: tens per box); with thousands per box (FULL far sets) the row
-  // sums dominate and want every workgroup the grid can hold.
-  if (from_parts && mode == 1 && small && p.n_pairs() <= 40 * p.n_box) {
+  // One wavefront per box while a box has up to a few hundred partial rows
+  // on average (interaction lists: tens); with thousands per box (FULL far
+  // sets) the row sums want a whole workgroup per box.
+  const bool few_rows = p.n_pairs() <= 256 * p.n_box;
+  if (from_parts && mode == 1 && small && few_rows) {
     // persistent: two resident workgroups per compute unit
-    const unsigned groups = (unsigned)std::min<int64_t>(p.n_box, 2 * 256);
-    UBF_LAUNCH(ev, (disaggregate_pipe_kernel<21>), dim3(groups, nrhs), dim3(kBlock), s, part,
-               p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
+    const unsigned wgs = (unsigned)((p.n_box + kBlock / 64 - 1) / (kBlock / 64));
+    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, false>), dim3(wgs, nrhs), dim3(kBlock), s,
+               part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
+               p.n_box, nb_total, p.nu, p.kh);
+  } else if (from_parts && mode == 0 && small && few_rows) {
+    const unsigned wgs = (unsigned)((p.n_box + kBlock / 64 - 1) / (kBlock / 64));
+    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, true>), dim3(wgs, nrhs), dim3(kBlock), s,
+               part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
                p.n_box, nb_total, p.nu, p.kh);
   } else if (from_parts) {
     if (small) UBF_DISAGG(true, 21); else UBF_DISAGG(true, 49);
