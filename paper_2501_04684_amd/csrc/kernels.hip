@@ -959,13 +959,12 @@ __global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
 
 // Stage 3 with one wavefront per box (E_j from the partial rows, N_u <= 84;
 // T_j = S_j^T, or y_j = E_j with IDENT): no workgroup barriers on the box's
-// path. Lane l < R4
-// sums float4 l of the box's partial rows (several rows in flight); the sums
-// go to the wavefront's own LDS slot (672 bytes) and come back as this
-// lane's rows of E_j; then 16 columns of S_j per pass, four lanes per column
-// (lane group q takes rows q, q + 4, ...), read from global memory and
-// reduced across the four lanes by shuffles. Same arithmetic as
-// disaggregate_kernel except the order of the partial-row sum.
+// path. Lane l < R4 sums float4 l of the box's partial rows (16 rows in
+// flight); the sums go to the wavefront's own LDS slot (672 bytes) and come
+// back as this lane's rows of E_j; then four columns of S_j per pass, 16
+// lanes per column, read from global memory and reduced across the 16 lanes
+// by shuffles. Same arithmetic as disaggregate_kernel except the order of
+// the sums.
 template <int EQ, bool IDENT>
 __global__ __launch_bounds__(kBlock) void disaggregate_wave_kernel(
     const float* __restrict__ part, const int32_t* __restrict__ test_ptr, int64_t n_pairs,
@@ -1012,11 +1011,15 @@ __global__ __launch_bounds__(kBlock) void disaggregate_wave_kernel(
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const float* Es = reinterpret_cast<const float*>(Es4[wave]);
-  const int q = lane >> 4;
-  float er[EQ], ei[EQ];
+  // 16 lanes per column: lane group cs = lane / 16 takes column c0 + cs and
+  // lane q = lane % 16 rows q, q + 16, ...; each load instruction reads four
+  // whole 128-byte lines of S_j
+  constexpr int RQ = (EQ * 4 + 15) / 16;  // rows per lane (N_u <= 4 EQ)
+  const int q = lane & 15, cs = lane >> 4;
+  float er[RQ], ei[RQ];
 #pragma unroll
-  for (int i = 0; i < EQ; ++i) {
-    const int u = min(q + 4 * i, nu - 1);
+  for (int i = 0; i < RQ; ++i) {
+    const int u = min(q + 16 * i, nu - 1);
     er[i] = Es[u];
     ei[i] = Es[nu + u];
   }
@@ -1024,24 +1027,25 @@ __global__ __launch_bounds__(kBlock) void disaggregate_wave_kernel(
   const int64_t nb = nb_ptr[j + 1] - start;
   const float2* Sb = S + start * nu;
   float2* yb = y + (int64_t)r * nb_total + start;
-#pragma unroll 2
-  for (int64_t c0 = 0; c0 < nb; c0 += 16) {
-    const int64_t c = c0 + (lane & 15);
+#pragma unroll 4
+  for (int64_t c0 = 0; c0 < nb; c0 += 4) {
+    const int64_t c = c0 + cs;
     const float2* col = Sb + min(c, nb - 1) * nu;
-    float2 sv[EQ];
+    float2 sv[RQ];
 #pragma unroll
-    for (int i = 0; i < EQ; ++i) sv[i] = col[min(q + 4 * i, nu - 1)];
+    for (int i = 0; i < RQ; ++i) sv[i] = col[min(q + 16 * i, nu - 1)];
     float sr = 0.f, si = 0.f;
 #pragma unroll
-    for (int i = 0; i < EQ; ++i)
-      if (q + 4 * i < nu) {
+    for (int i = 0; i < RQ; ++i)
+      if (q + 16 * i < nu) {
         sr = fmaf(sv[i].x, er[i], fmaf(-sv[i].y, ei[i], sr));
         si = fmaf(sv[i].x, ei[i], fmaf(sv[i].y, er[i], si));
       }
-    sr += __shfl_xor(sr, 16, 64);
-    si += __shfl_xor(si, 16, 64);
-    sr += __shfl_xor(sr, 32, 64);
-    si += __shfl_xor(si, 32, 64);
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      sr += __shfl_xor(sr, o, 64);
+      si += __shfl_xor(si, o, 64);
+    }
     if (c < nb && q == 0) yb[c] = make_float2(sr, si);
   }
 }
