@@ -148,6 +148,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5, 6],
                     help="synthetic workload index (2 = 3,338-box shell; 6 = the "
                          "2-wavelength sphere with trained translation networks)")
+    ap.add_argument("--variant", choices=["shell", "plate"], default="shell",
+                    help="workload 3: the shell or the 0.5 x 2 x 8 plate at a = 0.125")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -719,7 +721,8 @@ def main():
         return bench_serve(args, U, W, torch)
     if args.workload == 6:
         return bench_networks(args, U, W, torch)
-    w = W.config(args.workload, far_mode=args.far_mode)
+    extra = {"variant": args.variant} if args.workload == 3 else {}
+    w = W.config(args.workload, far_mode=args.far_mode, **extra)
     if args.far_mode == "full":
         w.name += "_full"
         args.steps = args.steps if args.steps_given else 100
