@@ -88,11 +88,6 @@ __device__ inline float4 load_once(const float4* p) {
   return make_float4(q.x, q.y, q.z, q.w);
 }
 
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // Workgroup ids are dealt round-robin to the 8 XCDs (id % 8). Remap so that
 // XCD x works on a contiguous block of work; work is grouped by offset, so
@@ -1027,7 +1022,6 @@ __global__ __launch_bounds__(kBlock) void disaggregate_wave_kernel(
   const int64_t nb = nb_ptr[j + 1] - start;
   const float2* Sb = S + start * nu;
   float2* yb = y + (int64_t)r * nb_total + start;
-#pragma unroll 4
   for (int64_t c0 = 0; c0 < nb; c0 += 4) {
     const int64_t c = c0 + cs;
     const float2* col = Sb + min(c, nb - 1) * nu;
