@@ -159,20 +159,33 @@ __device__ inline int xcd_item(int bid, int grid) { return (bid & 7) * (grid >> 
 
 // The 32 source box vectors of pairs begin + c0 .. begin + c0 + ncol - 1
 // (planar padded, 2*KH floats each) into LDS columns of pitch XP floats;
-// columns past ncol are zero.
+// columns past ncol are zero. All of a thread's index loads go out first,
+// then all its vector loads, then the LDS writes, so the dependent loads
+// overlap instead of forming one chain per piece.
 template <int KH, int XP>
 __device__ inline void stage_columns(floatx4* xs4, const float* __restrict__ Pr,
                                      const int32_t* __restrict__ pair_src, int first,
                                      int ncol) {
-  constexpr int Q = 2 * KH / 4;  // 16-byte pieces of a box vector
-  for (int i = threadIdx.x; i < 32 * Q; i += kBlock) {
+  constexpr int Q = 2 * KH / 4;                      // 16-byte pieces of a box vector
+  constexpr int IT = (32 * Q + kBlock - 1) / kBlock;  // pieces per thread
+  int src[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int c = (threadIdx.x + k * kBlock) / Q;
+    src[k] = pair_src[first + min(c, ncol - 1)];
+  }
+  floatx4 v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int i = threadIdx.x + k * kBlock;
     const int c = i / Q, q = i - c * Q;
-    floatx4 v = {0.f, 0.f, 0.f, 0.f};
-    if (c < ncol) {
-      const int src = pair_src[first + c];
-      v = reinterpret_cast<const floatx4*>(Pr + (int64_t)src * 2 * KH)[q];
-    }
-    xs4[c * (XP / 4) + q] = v;
+    v[k] = reinterpret_cast<const floatx4*>(Pr + (int64_t)src[k] * 2 * KH)[min(q, Q - 1)];
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    const int c = i / Q, q = i - c * Q;
+    if (i < 32 * Q) xs4[c * (XP / 4) + q] = c < ncol ? v[k] : floatx4{0.f, 0.f, 0.f, 0.f};
   }
 }
 
