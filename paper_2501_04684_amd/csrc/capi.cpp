@@ -177,6 +177,7 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
       {L.table, p.split() ? (const void*)p.table_bf16.data() : (const void*)p.table.data(),
        p.table_bytes()},
       {L.chunks, p.chunks.data(), p.chunks.size() * sizeof(int32_t)},
+      {L.items, p.items.data(), p.items.size() * sizeof(int32_t)},
       {L.wg_ptr, p.wg_ptr.data(), p.wg_ptr.size() * sizeof(int32_t)},
       {L.pair_src, p.pair_src.data(), p.pair_src.size() * sizeof(int32_t)},
       {L.pair_dst, p.pair_dst.data(), p.pair_dst.size() * sizeof(int32_t)},
@@ -196,6 +197,7 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
   p.max_nrhs = max_nrhs;
   p.d_table = (float*)(ws + L.table);
   p.d_chunks = (int32_t*)(ws + L.chunks);
+  p.d_items = (int32_t*)(ws + L.items);
   p.d_wg_ptr = (int32_t*)(ws + L.wg_ptr);
   p.d_pair_src = (int32_t*)(ws + L.pair_src);
   p.d_test_ptr = (int32_t*)(ws + L.test_ptr);

@@ -33,7 +33,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kBlock = 256;
-static_assert(kChunk == 128, "a chunk is four quarters of 32 pairs");
 
 // Network image of one offset, in floats. The weights are stored in the
 // matrix-core fragment order of the kernel below (sign of -W1i / -W2i
@@ -151,66 +150,100 @@ __device__ inline void rowblock_products(floatx16 (&acc)[PER], const floatx4* co
   }
 }
 
-// Work item of this workgroup: consecutive items (the quarters of a chunk,
-// then the chunks of an offset, which share their weights) go to the same
-// XCD, whose L2 then fetches those weights once. The hardware deals
-// workgroups to the 8 XCDs round robin; the grid is a multiple of 8.
+// Work item of this workgroup: consecutive items (the 32-pair pieces of an
+// offset's pairs, which share their weights) go to the same XCD, whose L2
+// then fetches those weights once, and every XCD gets the same number of
+// items. The hardware deals workgroups to the 8 XCDs round robin; the grid
+// is a multiple of 8.
 __device__ inline int xcd_item(int bid, int grid) { return (bid & 7) * (grid >> 3) + (bid >> 3); }
 
-// The 32 source box vectors of pairs begin + c0 .. begin + c0 + ncol - 1
-// (planar padded, 2*KH floats each) into LDS columns of pitch XP floats;
-// columns past ncol are zero. All of a thread's index loads go out first,
-// then all its vector loads, then the LDS writes, so the dependent loads
-// overlap instead of forming one chain per piece.
-template <int KH, int XP>
-__device__ inline void stage_columns(floatx4* xs4, const float* __restrict__ Pr,
-                                     const int32_t* __restrict__ pair_src, int first,
-                                     int ncol) {
-  constexpr int Q = 2 * KH / 4;                      // 16-byte pieces of a box vector
-  constexpr int IT = (32 * Q + kBlock - 1) / kBlock;  // pieces per thread
+// Column staging of one work item: the source box vectors (planar padded,
+// [re | im] of KH floats each) of pairs first .. first + ncol - 1 go to LDS
+// columns of pitch XP floats, columns past ncol zero. With PASSES = 2 the k
+// range is staged in two halves: pass p holds floats [p KH/2, (p + 1) KH/2)
+// of the real and of the imaginary part ([re | im] of KH/2 floats), which
+// halves the LDS a workgroup needs. The index loads are made once; each
+// pass issues all of a thread's vector loads before its LDS writes, so the
+// loads overlap instead of forming one chain per piece.
+template <int KH, int XP, int PASSES>
+struct ColumnStager {
+  static constexpr int KP = KH / PASSES;                 // floats of a part per pass
+  static constexpr int Q = 2 * KP / 4;                   // 16-byte pieces per column
+  static constexpr int IT = (32 * Q + kBlock - 1) / kBlock;  // pieces per thread
+  static_assert(KP % 4 == 0 && XP >= 2 * KP, "pass width");
   int src[IT];
+
+  __device__ ColumnStager(const int32_t* __restrict__ pair_src, int first, int ncol) {
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int c = (threadIdx.x + k * kBlock) / Q;
-    src[k] = pair_src[first + min(c, ncol - 1)];
+    for (int k = 0; k < IT; ++k) {
+      const int c = (threadIdx.x + k * kBlock) / Q;
+      src[k] = pair_src[first + min(c, ncol - 1)];
+    }
   }
-  floatx4 v[IT];
+
+  __device__ void stage(floatx4* xs4, const float* __restrict__ Pr, int ncol, int pass) const {
+    floatx4 v[IT];
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int i = threadIdx.x + k * kBlock;
-    const int c = i / Q, q = i - c * Q;
-    v[k] = reinterpret_cast<const floatx4*>(Pr + (int64_t)src[k] * 2 * KH)[min(q, Q - 1)];
-  }
+    for (int k = 0; k < IT; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      const int q = min(i % Q, Q - 1);
+      const int part = q / (Q / 2), qq = q - part * (Q / 2);
+      v[k] = reinterpret_cast<const floatx4*>(Pr + (int64_t)src[k] * 2 * KH + part * KH +
+                                              pass * KP)[qq];
+    }
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int i = threadIdx.x + k * kBlock;
-    const int c = i / Q, q = i - c * Q;
-    if (i < 32 * Q) xs4[c * (XP / 4) + q] = c < ncol ? v[k] : floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < IT; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      const int c = i / Q, q = i - c * Q;
+      if (i < 32 * Q) xs4[c * (XP / 4) + q] = c < ncol ? v[k] : floatx4{0.f, 0.f, 0.f, 0.f};
+    }
   }
+};
+
+// Passes of the column staging: two where a k half is a whole number of
+// four-float groups and the single pass would need more than 32 KB of LDS.
+__host__ __device__ constexpr int staging_passes(int kh) {
+  return (kh % 8 == 0 && 32 * (2 * kh + 4) * 4 > 32768) ? 2 : 1;
 }
 
-// One workgroup per 32 pairs of a chunk (a chunk holds up to 128 pairs of
-// one offset; work item 4 * chunk + quarter, XCD-aware), three per CU. The 32
-// source box vectors are staged in LDS; wavefront w computes layer-1 row
-// blocks w, w + 4, ... (A from the network image in fragment order, B from
-// LDS); after a barrier it writes bias + CReLU into the hidden tile, which
-// reuses the staged vectors' LDS, and after another barrier computes
-// layer-2 row blocks w, w + 4, ... the same way. Lane l owns pair column
+// Work item k of this workgroup (XCD-aware, see xcd_item); false for the
+// grid's padding.
+__device__ inline bool load_item(const int32_t* __restrict__ items, int n_items, int& o,
+                                 int& first, int& ncol) {
+  const int k = xcd_item(blockIdx.x, gridDim.x);
+  if (k >= n_items) return false;
+  const int4 it = reinterpret_cast<const int4*>(items)[k];
+  o = it.x;
+  first = it.y;
+  ncol = it.z;
+  return true;
+}
+
+// One workgroup per work item (up to 32 pairs of one offset, XCD-aware);
+// at N_u = 192 the LDS of the two-pass staging lets five share a CU, so
+// that the items of a product run in one round. The source box vectors are
+// staged in LDS; wavefront w computes layer-1 row blocks w, w + 4, ... (A
+// from the network image in fragment order, B from LDS), over the k range
+// of each staging pass in turn; after a barrier it writes bias + CReLU into
+// the hidden tile, which reuses the staged vectors' LDS, and after another
+// barrier computes layer-2 row blocks w, w + 4, ... the same way. Lane l owns pair column
 // l % 32; its 4-row pieces of each output block go to the pair's partial
 // row, whose positions are the output rows [Er | Ei].
 template <int NU, int HB>
-__global__ __launch_bounds__(kBlock, 3) void translate_cvfcnn_kernel(
-    const float* __restrict__ net, const int32_t* __restrict__ chunks,
+__global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
+    const float* __restrict__ net, const int32_t* __restrict__ items,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
     const float* __restrict__ P, const float* __restrict__ linf, float* __restrict__ part,
-    int64_t n_box, int64_t n_pairs, int hidden, int n_chunks) {
+    int64_t n_box, int64_t n_pairs, int hidden, int n_items) {
   constexpr int KH = (NU + 3) & ~3;
   constexpr int HP = 32 * HB;
   constexpr int64_t NF = image_floats(NU, KH, HP);
   constexpr int B1_OFF = 2 * HB * (KH / 4) * 256;
   constexpr int W2_OFF = B1_OFF + 2 * HP;
   constexpr int B2_OFF = W2_OFF + ((2 * NU + 31) / 32) * (HP / 4) * 256;
-  constexpr int XP = 2 * KH + 4;     // LDS pitch of a staged box vector
+  constexpr int PASSES = staging_passes(KH);
+  constexpr int KP = KH / PASSES;
+  constexpr int XP = 2 * KP + 4;     // LDS pitch of a staged box vector
   constexpr int HPT = 2 * HP + 4;    // LDS pitch of a hidden column
   constexpr int OB = (2 * NU + 31) / 32;
   constexpr int PSTR = 2 * KH;
@@ -220,23 +253,18 @@ __global__ __launch_bounds__(kBlock, 3) void translate_cvfcnn_kernel(
   float* xs = reinterpret_cast<float*>(xs4);
   float* hs = xs;
 
-  const int item = xcd_item(blockIdx.x, gridDim.x);
-  if (item >= 4 * n_chunks) return;  // grid padding
-  const int chunk = item >> 2;
-  const int c0 = (item & 3) * 32;
-  const int o = chunks[4 * chunk], begin = chunks[4 * chunk + 1];
-  const int count = chunks[4 * chunk + 2];
-  if (c0 >= count) return;  // whole workgroup
-  const int ncol = min(32, count - c0);
+  int o, first, ncol;
+  if (!load_item(items, n_items, o, first, ncol)) return;  // grid padding
   const int rhs = blockIdx.y;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int r = lane & 31, h = lane >> 5;
   const float* no = net + (size_t)o * NF;
   const float* Pr = P + (int64_t)rhs * n_box * 2 * KH;
 
-  stage_columns<KH, XP>(xs4, Pr, pair_src, begin + c0, ncol);
+  const ColumnStager<KH, XP, PASSES> stager(pair_src, first, ncol);
+  stager.stage(xs4, Pr, ncol, 0);
   const bool live = r < ncol;
-  const int pos = begin + c0 + min(r, ncol - 1);
+  const int pos = first + min(r, ncol - 1);
   const int src = pair_src[pos];
   const int dst = pair_dst[pos];
   const float s = linf[(int64_t)rhs * n_box + src];
@@ -257,9 +285,20 @@ __global__ __launch_bounds__(kBlock, 3) void translate_cvfcnn_kernel(
       arow[i] = reinterpret_cast<const floatx4*>(no) + (size_t)rb * (KH / 4) * 64 + lane;
       acc[i] = floatx16{};
     }
-    if (wave < NB)  // wave-uniform
-      rowblock_products<PER1, KH / 4>(acc, arow,
-                                      reinterpret_cast<const floatx4*>(xs + r * XP + h * KH));
+#pragma unroll
+    for (int pass = 0; pass < PASSES; ++pass) {
+      if (pass > 0) {
+        __syncthreads();  // every wavefront is done with the previous pass
+        stager.stage(xs4, Pr, ncol, pass);
+        __syncthreads();
+      }
+      const floatx4* ap[PER1];
+#pragma unroll
+      for (int i = 0; i < PER1; ++i) ap[i] = arow[i] + pass * (KP / 4) * 64;
+      if (wave < NB)  // wave-uniform
+        rowblock_products<PER1, KP / 4>(acc, ap,
+                                        reinterpret_cast<const floatx4*>(xs + r * XP + h * KP));
+    }
     __syncthreads();  // every wavefront is done with the staged vectors
 #pragma unroll
     for (int i = 0; i < PER1; ++i) {
@@ -322,37 +361,35 @@ __global__ __launch_bounds__(kBlock, 3) void translate_cvfcnn_kernel(
 }
 
 // Operator-table product E = G_w P for box sizes whose columns do not fit
-// in registers (N_u = 192): the scheme of the network kernel's second
-// layer with K = 2 N_u, A read from the FP32 table in fragment order (per
+// in registers (N_u = 192): the scheme of the network kernel's first layer
+// with M = K = 2 N_u, A read from the FP32 table in fragment order (per
 // offset: 2 N_u / 32 row blocks of [[Gr, -Gi], [Gi, Gr]], KH/4 groups, 64
-// lanes x 4 floats) and B from the staged box vectors.
+// lanes x 4 floats) and B from the box vectors staged in two passes.
 template <int NU>
-__global__ __launch_bounds__(kBlock, 2) void translate_staged_kernel(
-    const float* __restrict__ table, const int32_t* __restrict__ chunks,
+__global__ __launch_bounds__(kBlock, 4) void translate_staged_kernel(
+    const float* __restrict__ table, const int32_t* __restrict__ items,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
     const float* __restrict__ P, float* __restrict__ part, int64_t n_box, int64_t n_pairs,
-    int n_chunks) {
+    int n_items) {
   constexpr int KH = (NU + 3) & ~3;
-  constexpr int XP = 2 * KH + 4;
+  constexpr int PASSES = staging_passes(KH);
+  constexpr int KP = KH / PASSES;
+  constexpr int XP = 2 * KP + 4;
   constexpr int OB = (2 * NU + 31) / 32;
   constexpr int PSTR = 2 * KH;
   __shared__ floatx4 xs4[32 * XP / 4];
   const float* xs = reinterpret_cast<const float*>(xs4);
 
-  const int item = xcd_item(blockIdx.x, gridDim.x);
-  if (item >= 4 * n_chunks) return;  // grid padding
-  const int chunk = item >> 2;
-  const int c0 = (item & 3) * 32;
-  const int o = chunks[4 * chunk], begin = chunks[4 * chunk + 1];
-  const int count = chunks[4 * chunk + 2];
-  if (c0 >= count) return;  // whole workgroup
-  const int ncol = min(32, count - c0);
+  int o, first, ncol;
+  if (!load_item(items, n_items, o, first, ncol)) return;  // grid padding
   const int rhs = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
-  stage_columns<KH, XP>(xs4, P + (int64_t)rhs * n_box * 2 * KH, pair_src, begin + c0, ncol);
+  const float* Pr = P + (int64_t)rhs * n_box * 2 * KH;
+  const ColumnStager<KH, XP, PASSES> stager(pair_src, first, ncol);
+  stager.stage(xs4, Pr, ncol, 0);
   const bool live = r < ncol;
-  const int dst = pair_dst[begin + c0 + min(r, ncol - 1)];
+  const int dst = pair_dst[first + min(r, ncol - 1)];
   __syncthreads();
   const floatx4* Go = reinterpret_cast<const floatx4*>(table) + (size_t)o * OB * (KH / 4) * 64;
   float* prow = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
@@ -364,8 +401,18 @@ __global__ __launch_bounds__(kBlock, 2) void translate_staged_kernel(
     arow[i] = Go + (size_t)min(wave + 4 * i, OB - 1) * (KH / 4) * 64 + lane;
     acc[i] = floatx16{};
   }
-  rowblock_products<PER, KH / 4>(acc, arow,
-                                 reinterpret_cast<const floatx4*>(xs + r * XP + h * KH));
+#pragma unroll
+  for (int pass = 0; pass < PASSES; ++pass) {
+    if (pass > 0) {
+      __syncthreads();  // every wavefront is done with the previous pass
+      stager.stage(xs4, Pr, ncol, pass);
+      __syncthreads();
+    }
+    const floatx4* ap[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) ap[i] = arow[i] + pass * (KP / 4) * 64;
+    rowblock_products<PER, KP / 4>(acc, ap, reinterpret_cast<const floatx4*>(xs + r * XP + h * KP));
+  }
   if (live) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -426,19 +473,19 @@ int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs
                             const StageEvents* ev) {
   hipStream_t s = (hipStream_t)stream;
   const int64_t rows = (int64_t)nrhs * p.n_box;
-  const int nch = (int)p.n_chunks();
+  const int nit = (int)p.n_items();
   hipEvent_t t0 = ev ? ev->start : nullptr, t1 = ev ? ev->stop : nullptr;
-  hipEvent_t t_linf = nch == 0 ? t1 : nullptr;
+  hipEvent_t t_linf = nit == 0 ? t1 : nullptr;
   UBF_LAUNCH(t0, t_linf, linf_kernel, dim3((unsigned)((rows + 3) / 4)), s, P, p.d_box_scale,
              rows, p.nu, p.kh);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || nch == 0) return (int)e;
-  const dim3 grid((unsigned)((4 * nch + 7) / 8 * 8), nrhs);
+  if (e != hipSuccess || nit == 0) return (int)e;
+  const dim3 grid((unsigned)((nit + 7) / 8 * 8), nrhs);
   hipEvent_t none = nullptr;
 #define UBF_NET(NU, HB)                                                                    \
-  UBF_LAUNCH(none, t1, (translate_cvfcnn_kernel<NU, HB>), grid, s, p.d_net, p.d_chunks,    \
+  UBF_LAUNCH(none, t1, (translate_cvfcnn_kernel<NU, HB>), grid, s, p.d_net, p.d_items,     \
              p.d_pair_src, p.d_pair_dst, P, p.d_box_scale, part, p.n_box, p.n_pairs(),     \
-             p.hidden, nch)
+             p.hidden, nit)
   const bool wide = p.hidden > 32;
   switch (p.nu) {
     case 24: if (wide) UBF_NET(24, 2); else UBF_NET(24, 1); break;
@@ -455,9 +502,9 @@ bool staged_translate_supported(const Plan& p) { return !p.split() && p.nu == 19
 int launch_translate_staged(const Plan& p, const float* P, float* part, int nrhs, void* stream,
                             const StageEvents* ev) {
   hipStream_t s = (hipStream_t)stream;
-  const int nch = (int)p.n_chunks();
+  const int nit = (int)p.n_items();
   hipEvent_t t0 = ev ? ev->start : nullptr, t1 = ev ? ev->stop : nullptr;
-  if (nch == 0) {
+  if (nit == 0) {
     if (ev) {
       hipError_t e = hipEventRecord(t0, s);
       if (e == hipSuccess) e = hipEventRecord(t1, s);
@@ -466,9 +513,9 @@ int launch_translate_staged(const Plan& p, const float* P, float* part, int nrhs
     return 0;
   }
   if (p.nu != 192 || p.split()) return (int)hipErrorInvalidValue;
-  UBF_LAUNCH(t0, t1, translate_staged_kernel<192>, dim3((unsigned)((4 * nch + 7) / 8 * 8), nrhs),
-             s, p.d_table, p.d_chunks, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
-             p.n_pairs(), nch);
+  UBF_LAUNCH(t0, t1, translate_staged_kernel<192>, dim3((unsigned)((nit + 7) / 8 * 8), nrhs),
+             s, p.d_table, p.d_items, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
+             p.n_pairs(), nit);
   return (int)hipGetLastError();
 }
 #undef UBF_LAUNCH

@@ -305,6 +305,7 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   };
   L.table = take(p.table_bytes());
   L.chunks = take(p.chunks.size() * sizeof(int32_t));
+  L.items = take(p.items.size() * sizeof(int32_t));
   L.wg_ptr = take((size_t)(kMaxTranslateGroups + 1) * sizeof(int32_t));
   L.pair_src = take(p.pair_src.size() * sizeof(int32_t));
   L.pair_dst = take(p.pair_dst.size() * sizeof(int32_t));
@@ -484,6 +485,14 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
       P.chunks.push_back((int32_t)s);
       P.chunks.push_back((int32_t)std::min<int64_t>(kChunk, P.off_ptr[o + 1] - s));
       P.chunks.push_back(0);
+    }
+  P.items.clear();
+  for (int64_t o = 0; o < n_off; ++o)
+    for (int64_t s = P.off_ptr[o]; s < P.off_ptr[o + 1]; s += 32) {
+      P.items.push_back((int32_t)o);
+      P.items.push_back((int32_t)s);
+      P.items.push_back((int32_t)std::min<int64_t>(32, P.off_ptr[o + 1] - s));
+      P.items.push_back(0);
     }
 
   partition_groups(P, kTranslateGroups);

@@ -117,6 +117,9 @@ struct Plan {
   std::vector<int32_t> test_pos;   // ... as positions in the grouped order
   std::vector<int32_t> pair_dst;   // grouped position -> test-major position
   std::vector<int32_t> chunks;     // 4 per chunk: offset, begin, count, 0
+  // Work items of the kernels that stage box vectors in LDS: 4 per item of
+  // up to 32 consecutive pairs of one offset: offset, first pair, count, 0.
+  std::vector<int32_t> items;
   std::vector<int32_t> wg_ptr;     // chunk range of each translation workgroup
   int32_t n_orbits = 0;
 
@@ -137,6 +140,7 @@ struct Plan {
   int64_t n_pairs() const { return (int64_t)pair_src.size(); }
   int32_t n_off() const { return (int32_t)(offsets.size() / 3); }
   int64_t n_chunks() const { return (int64_t)(chunks.size() / 4); }
+  int64_t n_items() const { return (int64_t)(items.size() / 4); }
   int32_t n_groups() const { return (int32_t)wg_ptr.size() - 1; }
   int32_t n_scat() const { return (int32_t)scat_ptr.size() - 1; }
   size_t plane_floats() const { return (size_t)nu * kh; }
@@ -162,6 +166,7 @@ struct Plan {
   // Device pointers into the workspace.
   float* d_table = nullptr;
   int32_t* d_chunks = nullptr;
+  int32_t* d_items = nullptr;
   int32_t* d_wg_ptr = nullptr;
   int32_t* d_pair_src = nullptr;
   int32_t* d_test_ptr = nullptr;
@@ -189,7 +194,7 @@ struct Plan {
 
 // Workspace layout, in bytes from the workspace start.
 struct Layout {
-  size_t table, chunks, wg_ptr, pair_src, pair_dst, test_ptr, nb_ptr, P, part, off_scale,
+  size_t table, chunks, items, wg_ptr, pair_src, pair_dst, test_ptr, nb_ptr, P, part, off_scale,
       box_scale, total;
 };
 Layout workspace_layout(const Plan& p, int32_t max_nrhs);
