@@ -14,9 +14,10 @@
 //   [hr; hi] = [[W1r, -W1i], [W1i, W1r]] [xr; xi]   M = 2*HP, K = 2*NU
 //   [Er; Ei] = [[W2r, -W2i], [W2i, W2r]] [hr; hi]   M = 2*NU, K = 2*HP
 // with HP = the hidden width rounded up to 32 (hidden units past the
-// network's width are zero). The division by s is applied to the layer-1
-// accumulators and the product by s to the layer-2 results, so the staged
-// box vectors are used as they are.
+// network's width are zero). s is taken from the staged box vector in
+// LDS; the division by s is applied to the layer-1 accumulators and the
+// product by s to the layer-2 results, so the staged box vectors are used
+// as they are.
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -109,35 +110,20 @@ __global__ __launch_bounds__(kBlock) void network_pack_kernel(
   }
 }
 
-// Largest modulus of each box vector (planar padded FP32 rows of 2*kh
-// floats), one wavefront per row.
-__global__ __launch_bounds__(kBlock) void linf_kernel(const float* __restrict__ P,
-                                                      float* __restrict__ out,
-                                                      int64_t n_rows, int nu, int kh) {
-  const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (row >= n_rows) return;  // whole wavefronts
-  const int l = threadIdx.x & 63;
-  const float* Pb = P + row * 2 * kh;
-  float m = 0.f;
-  for (int u = l; u < nu; u += 64) {
-    const float re = Pb[u], im = Pb[kh + u];
-    m = fmaxf(m, sqrtf(fmaf(re, re, im * im)));
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-  if (l == 0) out[row] = m;
-}
-
 // acc[i] += A_i B for the PER row blocks a wavefront owns, over G groups of
 // four k-steps: per group one 16-byte A load per block and lane (fragment
 // order: arow[i] points at the lane's piece of group 0, the next group is
 // 64 pieces on) and one 16-byte B load from LDS shared by all blocks;
-// consecutive MFMAs go to different blocks' accumulators.
-template <int PER, int G>
+// consecutive MFMAs go to different blocks' accumulators. The group count
+// is G, or ng where it is given (a run-time count of at most G). The loop
+// is unrolled U times: measured best at two for the network kernel and at
+// one (rolled) for the operator-table kernel, whose three row blocks per
+// wavefront already hold three loads in flight.
+template <int PER, int G, int U>
 __device__ inline void rowblock_products(floatx16 (&acc)[PER], const floatx4* const (&arow)[PER],
-                                         const floatx4* brow) {
-#pragma unroll 2
-  for (int g = 0; g < G; ++g) {
+                                         const floatx4* brow, int ng = G) {
+#pragma unroll U
+  for (int g = 0; g < ng; ++g) {
     const floatx4 b = brow[g];
     floatx4 a[PER];
 #pragma unroll
@@ -233,8 +219,8 @@ template <int NU, int HB>
 __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
     const float* __restrict__ net, const int32_t* __restrict__ items,
     const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
-    const float* __restrict__ P, const float* __restrict__ linf, float* __restrict__ part,
-    int64_t n_box, int64_t n_pairs, int hidden, int n_items) {
+    const float* __restrict__ P, float* __restrict__ part, int64_t n_box, int64_t n_pairs,
+    int hidden, int n_items) {
   constexpr int KH = (NU + 3) & ~3;
   constexpr int HP = 32 * HB;
   constexpr int64_t NF = image_floats(NU, KH, HP);
@@ -250,6 +236,7 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
   // the hidden tile reuses the staged vectors' LDS once layer 1 has read them
   constexpr int TILE = 32 * (XP > HPT ? XP : HPT);
   __shared__ floatx4 xs4[TILE / 4];
+  __shared__ float col_scale[32];
   float* xs = reinterpret_cast<float*>(xs4);
   float* hs = xs;
 
@@ -264,11 +251,11 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
   const ColumnStager<KH, XP, PASSES> stager(pair_src, first, ncol);
   stager.stage(xs4, Pr, ncol, 0);
   const bool live = r < ncol;
-  const int pos = first + min(r, ncol - 1);
-  const int src = pair_src[pos];
-  const int dst = pair_dst[pos];
-  const float s = linf[(int64_t)rhs * n_box + src];
-  const float inv_s = s > 0.f ? 1.f / s : 0.f;
+  const int dst = pair_dst[first + min(r, ncol - 1)];
+  // l-inf norm of the staged columns: eight threads per column take the
+  // largest squared modulus over each pass's k range (components below N_u)
+  const int mc = t >> 3, mj = t & 7;
+  float m2 = 0.f, s = 0.f, inv_s = 0.f;
   __syncthreads();
 
   // layer 1: A row = hidden unit m of part (0: real, 1: imaginary); lane
@@ -296,10 +283,23 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
 #pragma unroll
       for (int i = 0; i < PER1; ++i) ap[i] = arow[i] + pass * (KP / 4) * 64;
       if (wave < NB)  // wave-uniform
-        rowblock_products<PER1, KP / 4>(acc, ap,
+        rowblock_products<PER1, KP / 4, 2>(acc, ap,
                                         reinterpret_cast<const floatx4*>(xs + r * XP + h * KP));
+#pragma unroll
+      for (int u = mj; u < KP; u += 8) {
+        if (pass * KP + u < NU) {
+          const float re = xs[mc * XP + u], im = xs[mc * XP + KP + u];
+          m2 = fmaxf(m2, fmaf(re, re, im * im));
+        }
+      }
     }
+    m2 = fmaxf(m2, __shfl_xor(m2, 4, 64));
+    m2 = fmaxf(m2, __shfl_xor(m2, 2, 64));
+    m2 = fmaxf(m2, __shfl_xor(m2, 1, 64));
+    if (mj == 0) col_scale[mc] = sqrtf(m2);
     __syncthreads();  // every wavefront is done with the staged vectors
+    s = col_scale[r];
+    inv_s = s > 0.f ? 1.f / s : 0.f;
 #pragma unroll
     for (int i = 0; i < PER1; ++i) {
       const int rb = wave + 4 * i;
@@ -333,8 +333,11 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
       arow[i] = reinterpret_cast<const floatx4*>(no + W2_OFF) + (size_t)ob * (HP / 4) * 64 + lane;
       acc[i] = floatx16{};
     }
-    rowblock_products<PER, HP / 4>(acc, arow,
-                                   reinterpret_cast<const floatx4*>(hs + r * HPT + h * HP));
+    // hidden units past the network's width are zero in the hidden tile and
+    // in W2: the k loop stops at the last group holding a unit
+    rowblock_products<PER, HP / 4, 2>(acc, arow,
+                                   reinterpret_cast<const floatx4*>(hs + r * HPT + h * HP),
+                                   (hidden + 3) / 4);
     if (live) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(kBlock, 4) void translate_staged_kernel(
     const floatx4* ap[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) ap[i] = arow[i] + pass * (KP / 4) * 64;
-    rowblock_products<PER, KP / 4>(acc, ap, reinterpret_cast<const floatx4*>(xs + r * XP + h * KP));
+    rowblock_products<PER, KP / 4, 1>(acc, ap, reinterpret_cast<const floatx4*>(xs + r * XP + h * KP));
   }
   if (live) {
 #pragma unroll
@@ -472,20 +475,20 @@ int launch_network_pack(const Plan& p, int hidden, const void* W1, const void* b
 int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs, void* stream,
                             const StageEvents* ev) {
   hipStream_t s = (hipStream_t)stream;
-  const int64_t rows = (int64_t)nrhs * p.n_box;
   const int nit = (int)p.n_items();
   hipEvent_t t0 = ev ? ev->start : nullptr, t1 = ev ? ev->stop : nullptr;
-  hipEvent_t t_linf = nit == 0 ? t1 : nullptr;
-  UBF_LAUNCH(t0, t_linf, linf_kernel, dim3((unsigned)((rows + 3) / 4)), s, P, p.d_box_scale,
-             rows, p.nu, p.kh);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || nit == 0) return (int)e;
+  if (nit == 0) {
+    if (ev) {
+      hipError_t e = hipEventRecord(t0, s);
+      if (e == hipSuccess) e = hipEventRecord(t1, s);
+      return (int)e;
+    }
+    return 0;
+  }
   const dim3 grid((unsigned)((nit + 7) / 8 * 8), nrhs);
-  hipEvent_t none = nullptr;
 #define UBF_NET(NU, HB)                                                                    \
-  UBF_LAUNCH(none, t1, (translate_cvfcnn_kernel<NU, HB>), grid, s, p.d_net, p.d_items,     \
-             p.d_pair_src, p.d_pair_dst, P, p.d_box_scale, part, p.n_box, p.n_pairs(),     \
-             p.hidden, nit)
+  UBF_LAUNCH(t0, t1, (translate_cvfcnn_kernel<NU, HB>), grid, s, p.d_net, p.d_items,       \
+             p.d_pair_src, p.d_pair_dst, P, part, p.n_box, p.n_pairs(), p.hidden, nit)
   const bool wide = p.hidden > 32;
   switch (p.nu) {
     case 24: if (wide) UBF_NET(24, 2); else UBF_NET(24, 1); break;

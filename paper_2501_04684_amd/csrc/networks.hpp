@@ -26,8 +26,8 @@ size_t network_image_bytes(const Plan& p, int hidden);
 int launch_network_pack(const Plan& p, int hidden, const void* W1, const void* b1,
                         const void* W2, const void* b2, float* img, void* stream);
 
-// Stage 2 with the plan's networks: the box vectors' l-inf norms into the
-// box-scale buffer, then the per-pair network products into the partial rows.
+// Stage 2 with the plan's networks: per-pair network products (each source
+// box vector scaled by its own l-inf norm) into the partial rows.
 int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs, void* stream,
                             const StageEvents* ev = nullptr);
 
