@@ -237,6 +237,7 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
   constexpr int TILE = 32 * (XP > HPT ? XP : HPT);
   __shared__ floatx4 xs4[TILE / 4];
   __shared__ float col_scale[32];
+  __shared__ float bias[2 * HP + 2 * KH];  // b1 (re, im), then b2 (re, im)
   float* xs = reinterpret_cast<float*>(xs4);
   float* hs = xs;
 
@@ -250,6 +251,8 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
 
   const ColumnStager<KH, XP, PASSES> stager(pair_src, first, ncol);
   stager.stage(xs4, Pr, ncol, 0);
+  for (int i = t; i < 2 * HP + 2 * KH; i += kBlock)
+    bias[i] = i < 2 * HP ? no[B1_OFF + i] : no[B2_OFF + i - 2 * HP];
   const bool live = r < ncol;
   const int dst = pair_dst[first + min(r, ncol - 1)];
   // l-inf norm of the staged columns: eight threads per column take the
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
       const int rb = wave + 4 * i;
       if (rb >= NB) continue;
       const int hpart = rb / HB, m0 = (rb % HB) * 32;
-      const float* b1 = no + B1_OFF + hpart * HP + m0;
+      const float* b1 = bias + hpart * HP + m0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         floatx4 v;
@@ -351,8 +354,8 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
               const int orow = r0 + jj;
-              const float b = orow < NU ? no[B2_OFF + orow]
-                                        : (orow < 2 * NU ? no[B2_OFF + KH + orow - NU] : 0.f);
+              const float b = orow < NU ? bias[2 * HP + orow]
+                                        : (orow < 2 * NU ? bias[2 * HP + KH + orow - NU] : 0.f);
               v[jj] = s * (acc[i][4 * q + jj] + b);
             }
             *reinterpret_cast<floatx4*>(prow + r0) = v;
