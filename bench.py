@@ -294,7 +294,8 @@ def bench_networks(args, U, W, torch):
     n_pairs, nu = info["n_pairs"], info["n_u"]
     flops = 16.0 * hidden * nu * n_pairs          # two complex layers per pair
     hp = 32 if hidden <= 32 else 64
-    issued = 2.0 * (2 * hp) * (2 * nu) * 2 * n_pairs   # both layers, padding included
+    hk = 4 * (-(-hidden // 4))          # layer 2's k loop ends at the last group of 4 units
+    issued = 2.0 * (2 * hp) * (2 * nu) * n_pairs + 2.0 * (2 * nu) * (2 * hk) * n_pairs
     tr = flops / (avg_us[1] * 1e-6) / 1e12
     stage_names = ["aggregate", "translate", "disaggregate"]
     dom = int(np.argmax(avg_us))
