@@ -968,7 +968,7 @@ __global__ __launch_bounds__(kBlock) void disaggregate_wave_kernel(
   constexpr int RU = 16;  // partial rows in flight per lane
   __shared__ float4 Es4[kBlock / 64][42];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (j >= n_box) return;  // whole wavefronts; no barriers below
   const int r = blockIdx.y;
   const int R4 = kh / 2;  // float4 per partial row (<= 42)
@@ -1174,17 +1174,17 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
   // on average (interaction lists: tens); with thousands per box (FULL far
   // sets) the row sums want a whole workgroup per box.
   const bool few_rows = p.n_pairs() <= 256 * p.n_box;
+  // One wavefront per workgroup, so that the dispatcher spreads the boxes
+  // evenly over the compute units (with four per workgroup a quarter of the
+  // CUs received 16 boxes and the rest 12, and the 16-box CUs set the time).
   if (from_parts && mode == 1 && small && few_rows) {
-    // persistent: two resident workgroups per compute unit
-    const unsigned wgs = (unsigned)((p.n_box + kBlock / 64 - 1) / (kBlock / 64));
-    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, false>), dim3(wgs, nrhs), dim3(kBlock), s,
-               part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
-               p.n_box, nb_total, p.nu, p.kh);
+    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, false>), dim3((unsigned)p.n_box, nrhs),
+               dim3(64), s, part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S,
+               (float2*)y, p.n_box, nb_total, p.nu, p.kh);
   } else if (from_parts && mode == 0 && small && few_rows) {
-    const unsigned wgs = (unsigned)((p.n_box + kBlock / 64 - 1) / (kBlock / 64));
-    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, true>), dim3(wgs, nrhs), dim3(kBlock), s,
-               part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
-               p.n_box, nb_total, p.nu, p.kh);
+    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, true>), dim3((unsigned)p.n_box, nrhs),
+               dim3(64), s, part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S,
+               (float2*)y, p.n_box, nb_total, p.nu, p.kh);
   } else if (from_parts) {
     if (small) UBF_DISAGG(true, 21); else UBF_DISAGG(true, 49);
   } else {
