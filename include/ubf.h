@@ -115,6 +115,9 @@ typedef struct ubf_info {
   int32_t precision;        /* enum ubf_precision of the plan */
   int32_t n_scatterers;     /* independent scatterers in the plan (>= 1) */
   int32_t translate_groups; /* persistent stage-2 workgroups per RHS */
+  int64_t n_items;          /* work items of the kernels that stage box vectors
+                               in LDS (N_u = 192, networks): up to 32 pairs of
+                               one offset each, per RHS */
 } ubf_info;
 
 typedef struct ubf_plan ubf_plan;

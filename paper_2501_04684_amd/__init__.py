@@ -66,7 +66,7 @@ class _Info(ctypes.Structure):
                 ("n_chunks", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("translate_flops", ctypes.c_double), ("mfma", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_scatterers", ctypes.c_int32),
-                ("translate_groups", ctypes.c_int32)]
+                ("translate_groups", ctypes.c_int32), ("n_items", ctypes.c_int64)]
 
 
 class _GmresStatus(ctypes.Structure):

@@ -515,6 +515,7 @@ int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
   out->precision = p.precision;
   out->n_scatterers = p.n_scat();
   out->translate_groups = p.n_groups();
+  out->n_items = p.n_items();
   return ok();
 }
 

@@ -141,6 +141,10 @@ def test_plan_far_set_matches_oracle(cfg):
             assert np.all(np.diff(t[o == oo]) > 0)
         # the work partition covers every pair once
         assert info["n_chunks"] >= -(-len(j) // 128)
+        # items of the LDS-staged kernels: each offset's pairs in pieces of 32
+        _, per_off = np.unique(off, axis=0, return_counts=True)
+        assert info["n_items"] == int(np.sum(-(-per_off // 32)))
+        assert info["n_chunks"] == int(np.sum(-(-per_off // 128)))
     finally:
         U.plan_destroy(plan)
 

@@ -46,7 +46,9 @@ def _field(boxes, a, k, n_d, mode, hidden, seed, max_nrhs=1):
     return ff, _nets(offs, *weights)
 
 
-@pytest.mark.parametrize("hidden", [16, 50, 64])
+# 1 and 7: widths that are not a multiple of the four hidden units of one
+# k group; 33: the first width of the 64-unit image
+@pytest.mark.parametrize("hidden", [1, 7, 16, 33, 50, 64])
 def test_identity_basis_config1(hidden):
     w = W.config(1, nrhs=2)
     announce("cvfcnn identity basis", w.name, "hidden", hidden)
@@ -82,18 +84,20 @@ def test_three_stages_synthetic_basis_config1():
     ff.close()
 
 
-def test_nd4_paper_shape():
-    # 3 N_d = 192 inputs, 50 hidden units (the paper's networks), FULL = ILIST
-    # on a 4^3 grid plus a ragged 4x4x5 grid
+@pytest.mark.parametrize("hidden", [33, 50, 64])
+def test_nd4_paper_shape(hidden):
+    # 3 N_d = 192 inputs (box vectors staged in two k passes), 50 hidden units
+    # as in the paper's networks and the edges of the 64-unit image; FULL =
+    # ILIST on a 4^3 grid plus a ragged 4x4x5 grid
     for boxes in (W.grid_boxes(4, 4, 4), W.grid_boxes(4, 4, 5)):
-        announce("cvfcnn n_d=4", len(boxes))
-        ff, nets = _field(boxes, 0.125, 2 * np.pi, 4, "ilist", 50, seed=5)
+        announce("cvfcnn n_d=4", len(boxes), "hidden", hidden)
+        ff, nets = _field(boxes, 0.125, 2 * np.pi, 4, "ilist", hidden, seed=5)
         x = W.complex_normal((1, len(boxes) * 192), seed=9)
         y = to_host(ff(to_dev(x)))
         P = x.reshape(1, len(boxes), 192).astype(np.complex128)
         ref = C.translate_cvfcnn(P, boxes, nets, "ilist").reshape(1, -1)
         err = rel_l2(y, ref)
-        print(f"n_d=4 {len(boxes)} boxes: rel_l2 = {err:.3e}")
+        print(f"n_d=4 {len(boxes)} boxes, hidden {hidden}: rel_l2 = {err:.3e}")
         assert err <= TOL
         ff.close()
 
