@@ -1174,17 +1174,23 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
   // on average (interaction lists: tens); with thousands per box (FULL far
   // sets) the row sums want a whole workgroup per box.
   const bool few_rows = p.n_pairs() <= 256 * p.n_box;
-  // One wavefront per workgroup, so that the dispatcher spreads the boxes
-  // evenly over the compute units (with four per workgroup a quarter of the
-  // CUs received 16 boxes and the rest 12, and the 16-box CUs set the time).
+  // When the boxes fill about two rounds of the chip (up to 16 resident
+  // wavefronts per CU), one wavefront per workgroup lets the dispatcher
+  // spread them evenly (with four per workgroup a quarter of the CUs of the
+  // 3,338-box shell received 16 boxes and the rest 12, and set the time).
+  // Larger launches keep four per workgroup: over many rounds the dynamic
+  // dispatch balances by itself, and a million one-wavefront workgroups
+  // cost more to dispatch (15% on the 314,171-box, 4-RHS batch).
+  const int wpg = (int64_t)p.n_box * nrhs <= 8192 ? 1 : kBlock / 64;
+  const dim3 wgrid((unsigned)((p.n_box + wpg - 1) / wpg), nrhs), wblock(64 * wpg);
   if (from_parts && mode == 1 && small && few_rows) {
-    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, false>), dim3((unsigned)p.n_box, nrhs),
-               dim3(64), s, part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S,
-               (float2*)y, p.n_box, nb_total, p.nu, p.kh);
+    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, false>), wgrid, wblock, s, part,
+               p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
+               p.n_box, nb_total, p.nu, p.kh);
   } else if (from_parts && mode == 0 && small && few_rows) {
-    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, true>), dim3((unsigned)p.n_box, nrhs),
-               dim3(64), s, part, p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S,
-               (float2*)y, p.n_box, nb_total, p.nu, p.kh);
+    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, true>), wgrid, wblock, s, part,
+               p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
+               p.n_box, nb_total, p.nu, p.kh);
   } else if (from_parts) {
     if (small) UBF_DISAGG(true, 21); else UBF_DISAGG(true, 49);
   } else {
