@@ -1180,7 +1180,7 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
   // 3,338-box shell received 16 boxes and the rest 12, and set the time).
   // Larger launches keep four per workgroup: over many rounds the dynamic
   // dispatch balances by itself, and a million one-wavefront workgroups
-  // cost more to dispatch (15% on the 314,171-box, 4-RHS batch).
+  // cost a little more to dispatch (1% on the 314,171-box, 4-RHS batch).
   const int wpg = (int64_t)p.n_box * nrhs <= 8192 ? 1 : kBlock / 64;
   const dim3 wgrid((unsigned)((p.n_box + wpg - 1) / wpg), nrhs), wblock(64 * wpg);
   if (from_parts && mode == 1 && small && few_rows) {
