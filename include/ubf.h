@@ -201,8 +201,9 @@ size_t ubf_network_bytes(const ubf_plan* plan, int32_t hidden);
  * [n_offsets][N_u]. They are converted on hip_stream into d_net (caller
  * owned, 16-byte aligned, at least ubf_network_bytes(plan, hidden) bytes),
  * which must stay allocated while the plan uses it; the weight arrays may
- * be freed once the stream has passed this call. hidden = 0 (pointers
- * ignored) returns stage 2 to the operator table. Needs a bound plan of
+ * be freed once the stream has passed this call (and may be NULL when the
+ * plan has no offsets). hidden = 0 (pointers ignored) returns stage 2 to
+ * the operator table. Needs a bound plan of
  * the FP32 form (precision 0). Any captured graph is discarded.
  * Errors: UBF_EINVAL (null, precision, n_d or hidden out of range,
  * misaligned image), UBF_ENOMEM (image too small), UBF_ESTATE (unbound),

@@ -482,7 +482,8 @@ int ubf_plan_set_networks(ubf_plan* plan, int32_t hidden, const void* d_W1, cons
     return fail(UBF_EINVAL, "hidden must be in 1.." + std::to_string(ubf::kMaxHidden));
   if (!ubf::network_shape_supported(p.nu, hidden))
     return fail(UBF_EINVAL, "networks need n_d 2, 3 or 4 (n_u 24, 81 or 192)");
-  if (!d_W1 || !d_b1 || !d_W2 || !d_b2 || !d_net)
+  // a plan without far pairs has no offsets and so no weights to convert
+  if ((p.n_off() > 0 && (!d_W1 || !d_b1 || !d_W2 || !d_b2)) || !d_net)
     return fail(UBF_EINVAL, "weight, bias or image pointer is NULL");
   if (((uintptr_t)d_net & 15) != 0) return fail(UBF_EINVAL, "image must be 16-byte aligned");
   const size_t need = ubf::network_image_bytes(p, hidden);

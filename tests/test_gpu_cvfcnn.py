@@ -102,6 +102,39 @@ def test_nd4_paper_shape(hidden):
         ff.close()
 
 
+@pytest.mark.parametrize("networks", [True, False])
+def test_nd4_degenerate_and_single_pair(networks):
+    # 192 coefficients per box, networks or the operator table staged in
+    # LDS: no far pair (one box; two adjacent boxes) gives zero, also with
+    # stage timing on; one far pair gives its single product
+    k = 2 * np.pi
+    for boxes in (np.array([[3, 3, 3]]), np.array([[0, 0, 0], [1, 1, 1]]),
+                  np.array([[0, 0, 0], [0, 0, 2]])):
+        announce("n_d=4 degenerate", boxes.tolist(), "networks", networks)
+        if networks:
+            ff, nets = _field(boxes, 0.125, k, 4, "ilist", 50, seed=11)
+        else:
+            ff = U.FarField(boxes, 0.125, k, 4, "ilist")
+        # one item per offset here (each offset holds a single pair)
+        assert ff.info["n_items"] == len(U.plan_offsets(ff.plan))
+        x = W.complex_normal((1, len(boxes) * 192), seed=13)
+        U.profile_begin(ff.plan, 2, 1)
+        y = to_host(ff(to_dev(x)))
+        torch.cuda.synchronize()
+        _, calls = U.profile_end(ff.plan, 2)
+        assert len(calls) == 1
+        P = x.reshape(1, len(boxes), 192).astype(np.complex128)
+        if ff.info["n_pairs"] == 0:
+            assert not np.any(y)
+        else:
+            ref = (C.translate_cvfcnn(P, boxes, nets, "ilist") if networks
+                   else O.translate(P, boxes, 0.125, k, 4))
+            err = rel_l2(y, ref.reshape(1, -1))
+            print(f"single pair, networks {networks}: rel_l2 = {err:.3e}")
+            assert err <= (TOL if networks else TOL_FP32)
+        ff.close()
+
+
 def test_linear_networks_reproduce_operator_table():
     # n_d = 2: W1 = [I; -I] and W2 = [G_w, -G_w] fit in 48 hidden units
     boxes = W.grid_boxes(6, 6, 4)
