@@ -10,6 +10,8 @@ the whole product stays below 1e-5, the bar used here. Exact linear networks
 (W1 = [I; -I], W2 = [G_w, -G_w], which compute G_w v) must reproduce the
 operator-table product within the FP32 bar of 1e-4.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -175,6 +177,30 @@ def test_shell3338_full_size():
     err = rel_l2(y, ref)
     print(f"{w.name}: rel_l2 = {err:.3e}")
     assert err <= TOL
+    ff.close()
+
+
+def test_sphere762_nd4_full_size_trained_networks():
+    # the network workload as bench.py times it: the 762-box sphere at
+    # a = 0.125 with the committed trained networks (16 orbit networks
+    # expanded to the 316 offsets), all 22,602 pairs, two right-hand sides
+    from paper_2501_04684_amd import training as T
+    path = os.path.join(os.path.dirname(U.__file__), "data", "networks_nd4_h50_a0.125.npz")
+    w = W.config(6, nrhs=2)
+    announce("cvfcnn trained networks", w.name)
+    orbit, meta = T.load(path)
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=2)
+    offs = U.plan_offsets(ff.plan)
+    weights = T.networks_for_plan(ff.plan, orbit, w.n_d)
+    ff.set_networks(*weights)
+    x = w.coefficients()
+    y = to_host(ff(to_dev(x)))
+    P = x.reshape(2, w.n_box, w.n_u).astype(np.complex128)
+    ref = C.translate_cvfcnn(P, w.boxes, _nets(offs, *weights), w.far_mode).reshape(2, -1)
+    for r in range(2):
+        err = rel_l2(y[r], ref[r])
+        print(f"{w.name} trained networks rhs {r}: rel_l2 = {err:.3e}")
+        assert err <= TOL
     ff.close()
 
 
