@@ -191,6 +191,17 @@ def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
     threads = max([p.get("num_threads", 1) for p in threadpool_info()
                    if p.get("user_api") == "blas"] or [1])
     rel = float(np.linalg.norm(y0_gpu - y_ref) / np.linalg.norm(y_ref))
+    # the same oracle on one BLAS thread, half the time budget
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"):
+        t1 = time.perf_counter()
+        n1 = 0
+        while True:
+            O.far_mvm(x, w.boxes, w.a, w.k, w.n_d, nb_ptr, S128, mode=w.far_mode)
+            n1 += 1
+            if time.perf_counter() - t1 >= budget_s / 2:
+                break
+        dt1 = time.perf_counter() - t1
     cpu_model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -204,6 +215,8 @@ def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
         "sample": f"{n} full far-zone MVMs of the same workload in {dt:.1f} s "
                   f"(NumPy FP64, grouped by offset; {len(os.sched_getaffinity(0))} "
                   f"host cores visible, {cpu_model})",
+        "single_thread": {"value": n1 / dt1, "unit": "MVM/s", "cores": 1,
+                          "sample": f"{n1} MVMs in {dt1:.1f} s on one BLAS thread"},
     }, rel
 
 
