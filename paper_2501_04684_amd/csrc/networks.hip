@@ -136,6 +136,33 @@ __device__ inline void rowblock_products(floatx16 (&acc)[PER], const floatx4* co
   }
 }
 
+// acc += A B for one row block, the loads of group g + D issued before the
+// products of group g (a ring of D + 1 register groups), so that loads stay
+// in flight across groups; the products are those of rowblock_products in
+// the same order. Measured 2 us faster than the two-way unrolled loop for
+// layer 1 of the network kernel (64.4 against 62.8 us).
+template <int G, int D>
+__device__ inline void rowblock_pipelined(floatx16& acc, const floatx4* arow, const floatx4* brow) {
+  static_assert(G >= D, "the prologue loads D groups");
+  floatx4 a[D + 1], b[D + 1];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    a[d] = arow[d * 64];
+    b[d] = brow[d];
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (g + D < G) {
+      a[(g + D) % (D + 1)] = arow[(g + D) * 64];
+      b[(g + D) % (D + 1)] = brow[g + D];
+    }
+    const floatx4 ac = a[g % (D + 1)], bc = b[g % (D + 1)];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[kk], bc[kk], acc, 0, 0, 0);
+  }
+}
+
 // Work item of this workgroup: consecutive items (the 32-pair pieces of an
 // offset's pairs, which share their weights) go to the same XCD, whose L2
 // then fetches those weights once, and every XCD gets the same number of
@@ -263,10 +290,10 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
 
   // layer 1: A row = hidden unit m of part (0: real, 1: imaginary); lane
   // half h multiplies the real (h = 0) or imaginary (h = 1) inputs. Row
-  // block rb = wave + 4 i (i < PER1); blocks past 2 HB are computed on
-  // block 0's rows and dropped.
+  // block rb = wave (2 HB <= 4 blocks, so at most one per wavefront).
   {
     constexpr int NB = 2 * HB, PER1 = (NB + 3) / 4;
+    static_assert(PER1 == 1, "one layer-1 row block per wavefront");
     floatx16 acc[PER1];
     const floatx4* arow[PER1];
 #pragma unroll
@@ -286,8 +313,8 @@ __global__ __launch_bounds__(kBlock, 5) void translate_cvfcnn_kernel(
 #pragma unroll
       for (int i = 0; i < PER1; ++i) ap[i] = arow[i] + pass * (KP / 4) * 64;
       if (wave < NB)  // wave-uniform
-        rowblock_products<PER1, KP / 4, 2>(acc, ap,
-                                        reinterpret_cast<const floatx4*>(xs + r * XP + h * KP));
+        rowblock_pipelined<KP / 4, 3>(acc[0], ap[0],
+                                      reinterpret_cast<const floatx4*>(xs + r * XP + h * KP));
 #pragma unroll
       for (int u = mj; u < KP; u += 8) {
         if (pass * KP + u < NU) {
