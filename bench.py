@@ -68,7 +68,7 @@ def issued_16bit_flops(form, nu, n_pairs, nrhs):
     return FORMS[form][1] * 2 * (-(-2 * nu // 32) * 32) * (2 * khb) * n_pairs * nrhs
 
 
-STAGE_KERNELS = {"aggregate": "aggregate_kernel",
+STAGE_KERNELS = {"aggregate": "::aggregate_kernel",  # not disaggregate_kernel
                  "translate_mfma": "translate_mfma_kernel",
                  "translate_split": "translate_split_kernel",
                  "disaggregate": "disaggregate_"}  # the per-box or the per-wavefront kernel

@@ -195,60 +195,99 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(
 
 // ---------------------------------------------------------------- stage 1
 
-// One workgroup per (box, rhs). Thread t owns row u = t % nu of S_i and
-// column group g = t / nu, so thread t reads S_i element t + nu*G*it: the
-// whole block streams S_i contiguously. The G column-group partial sums
-// are reduced through LDS.
+// One workgroup per (box, block of RB right-hand sides). Thread t owns row
+// u = t % nu of S_i and column group g = t / nu, so thread t reads S_i
+// element t + nu*G*it: the whole block streams S_i contiguously, once for
+// the RB vectors. The G column-group partial sums are reduced through LDS.
+template <int RB>
 __global__ __launch_bounds__(kBlock) void aggregate_kernel(
     const float2* __restrict__ x, const int64_t* __restrict__ nb_ptr,
     const float2* __restrict__ S, float* __restrict__ P, int64_t n_box,
-    int64_t nb_total, int nu, int kh, int khb, int mode, float* __restrict__ box_scale) {
-  __shared__ float2 red[kBlock];
+    int64_t nb_total, int nu, int kh, int khb, int mode, float* __restrict__ box_scale,
+    int nrhs) {
+  __shared__ float2 red[RB][kBlock];
   __shared__ float wmax[kBlock / 64];
   const int64_t i = blockIdx.x;
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);  // >= 1
   const int t = threadIdx.x;
   const int G = kBlock / nu;
   const int u = t % nu, g = t / nu;
   const int64_t start = nb_ptr[i];
   const int64_t nb = nb_ptr[i + 1] - start;
   const float2* Sb = S + start * nu;
-  const float2* xb = x + (int64_t)r * nb_total + start;
-  float ar = 0.f, ai = 0.f;
-  if (g < G) {
-#pragma unroll 9
-    for (int64_t c = g; c < nb; c += G) {
-      const float2 s = Sb[c * nu + u];
-      const float2 xv = xb[c];
-      ar = fmaf(s.x, xv.x, ar);
-      ar = fmaf(-s.y, xv.y, ar);
-      ai = fmaf(s.x, xv.y, ai);
-      ai = fmaf(s.y, xv.x, ai);
-    }
-  }
-  red[t] = make_float2(ar, ai);
-  __syncthreads();
-  float* Pb = P + ((int64_t)r * n_box + i) * (mode ? 2 * khb : 2 * kh);
-  const int len = mode ? khb : kh;  // <= kBlock: one coefficient per thread
-  float sr = 0.f, si = 0.f;
-  if (t < nu)
-    for (int gg = 0; gg < G; ++gg) {
-      sr += red[gg * nu + t].x;
-      si += red[gg * nu + t].y;
-    }
-  float inv = 1.f;
-  if (mode == 2) {  // FP16: the box vector's scale from its largest component
-    float m = fmaxf(fabsf(sr), fabsf(si));
+  const float2* xb = x + (int64_t)r0 * nb_total + start;
+  float ar[RB], ai[RB];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((t & 63) == 0) wmax[t >> 6] = m;
-    __syncthreads();
-    m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-    const float sc = box_scale_for(m);
-    inv = 1.f / sc;
-    if (t == 0) box_scale[(int64_t)r * n_box + i] = sc;
+  for (int q = 0; q < RB; ++q) ar[q] = ai[q] = 0.f;
+  if constexpr (RB == 1) {
+    if (g < G) {
+#pragma unroll 9
+      for (int64_t c = g; c < nb; c += G) {
+        const float2 s = Sb[c * nu + u];
+        const float2 xv = xb[c];
+        ar[0] = fmaf(s.x, xv.x, ar[0]);
+        ar[0] = fmaf(-s.y, xv.y, ar[0]);
+        ai[0] = fmaf(s.x, xv.y, ai[0]);
+        ai[0] = fmaf(s.y, xv.x, ai[0]);
+      }
+    }
+  } else {
+    // the block's x values go through LDS, 256 columns at a time, so that
+    // the loop's only global loads are those of S_i; vectors past the last
+    // one repeat it, and their sums are not stored
+    __shared__ float2 xs[RB][kBlock];
+    for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
+      const int64_t cn = min<int64_t>(kBlock, nb - c0);
+      if (c0 > 0) __syncthreads();  // every thread is done with the last tile
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+        if (t < cn) xs[q][t] = xb[(int64_t)min(q, nr - 1) * nb_total + c0 + t];
+      __syncthreads();
+      if (g < G) {
+#pragma unroll 5
+        for (int c = g; c < cn; c += G) {
+          const float2 s = Sb[(c0 + c) * nu + u];
+#pragma unroll
+          for (int q = 0; q < RB; ++q) {
+            const float2 xv = xs[q][c];
+            ar[q] = fmaf(s.x, xv.x, ar[q]);
+            ar[q] = fmaf(-s.y, xv.y, ar[q]);
+            ai[q] = fmaf(s.x, xv.y, ai[q]);
+            ai[q] = fmaf(s.y, xv.x, ai[q]);
+          }
+        }
+      }
+    }
   }
-  if (t < len) put_coef(Pb, t, sr, si, kh, khb, mode, inv);
+#pragma unroll
+  for (int q = 0; q < RB; ++q) red[q][t] = make_float2(ar[q], ai[q]);
+  __syncthreads();
+  const int len = mode ? khb : kh;  // <= kBlock: one coefficient per thread
+  for (int q = 0; q < nr; ++q) {
+    const int r = r0 + q;
+    float* Pb = P + ((int64_t)r * n_box + i) * (mode ? 2 * khb : 2 * kh);
+    float sr = 0.f, si = 0.f;
+    if (t < nu)
+      for (int gg = 0; gg < G; ++gg) {
+        sr += red[q][gg * nu + t].x;
+        si += red[q][gg * nu + t].y;
+      }
+    float inv = 1.f;
+    if (mode == 2) {  // FP16: the box vector's scale from its largest component
+      float m = fmaxf(fabsf(sr), fabsf(si));
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+      if ((t & 63) == 0) wmax[t >> 6] = m;
+      __syncthreads();
+      m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+      if (q + 1 < nr) __syncthreads();  // wmax is reused by the next vector
+      const float sc = box_scale_for(m);
+      inv = 1.f / sc;
+      if (t == 0) box_scale[(int64_t)r * n_box + i] = sc;
+    }
+    if (t < len) put_coef(Pb, t, sr, si, kh, khb, mode, inv);
+  }
 }
 
 // ---------------------------------------------------------------- stage 2
@@ -954,93 +993,106 @@ __global__ __launch_bounds__(kBlock, EQ <= 21 ? 3 : 2) void disaggregate_kernel(
 
 // Stage 3 with one wavefront per box (E_j from the partial rows, N_u <= 84;
 // T_j = S_j^T, or y_j = E_j with IDENT): no workgroup barriers on the box's
-// path. Lane l < R4 sums float4 l of the box's partial rows (16 rows in
-// flight); the sums go to the wavefront's own LDS slot (672 bytes) and come
-// back as this lane's rows of E_j; then four columns of S_j per pass, 16
-// lanes per column, read from global memory and reduced across the 16 lanes
-// by shuffles. Same arithmetic as disaggregate_kernel except the order of
-// the sums.
-template <int EQ, bool IDENT>
+// path. The wavefront serves a block of up to RB right-hand sides. For each,
+// lane l < R4 sums float4 l of the box's partial rows (16 rows in flight);
+// the sums go to the wavefront's own LDS slot (672 bytes per vector) and
+// come back as this lane's rows of E_j; then four columns of S_j per pass,
+// 16 lanes per column, read from global memory once for the RB vectors and
+// reduced across the 16 lanes by shuffles. Same arithmetic as
+// disaggregate_kernel except the order of the sums.
+template <int EQ, bool IDENT, int RB>
 __global__ __launch_bounds__(kBlock) void disaggregate_wave_kernel(
     const float* __restrict__ part, const int32_t* __restrict__ test_ptr, int64_t n_pairs,
     const int64_t* __restrict__ nb_ptr, const float2* __restrict__ S, float2* __restrict__ y,
-    int64_t n_box, int64_t nb_total, int nu, int kh) {
+    int64_t n_box, int64_t nb_total, int nu, int kh, int nrhs) {
   constexpr int RU = 16;  // partial rows in flight per lane
-  __shared__ float4 Es4[kBlock / 64][42];
+  __shared__ float4 Es4[kBlock / 64][RB][42];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (j >= n_box) return;  // whole wavefronts; no barriers below
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);  // >= 1
   const int R4 = kh / 2;  // float4 per partial row (<= 42)
   const int p0 = test_ptr[j], p1 = test_ptr[j + 1];
-  const float4* pr = reinterpret_cast<const float4*>(part) + (int64_t)r * n_pairs * R4;
-  if (lane < R4) {
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int p = p0; p < p1; p += RU) {
-      float4 v[RU];
+  for (int qr = 0; qr < nr; ++qr) {
+    const int r = r0 + qr;
+    const float4* pr = reinterpret_cast<const float4*>(part) + (int64_t)r * n_pairs * R4;
+    if (lane < R4) {
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int p = p0; p < p1; p += RU) {
+        float4 v[RU];
 #pragma unroll
-      for (int i = 0; i < RU; ++i) v[i] = load_once(&pr[(int64_t)min(p + i, p1 - 1) * R4 + lane]);
+        for (int i = 0; i < RU; ++i)
+          v[i] = load_once(&pr[(int64_t)min(p + i, p1 - 1) * R4 + lane]);
 #pragma unroll
-      for (int i = 0; i < RU; ++i)
-        if (p + i < p1) {
-          acc.x += v[i].x;
-          acc.y += v[i].y;
-          acc.z += v[i].z;
-          acc.w += v[i].w;
-        }
-    }
-    if (IDENT) {  // y_j = E_j: this lane's four positions of [Er | Ei]
-      float2* yj = y + (int64_t)r * nb_total + j * nu;
-      const float a4[4] = {acc.x, acc.y, acc.z, acc.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int pos = 4 * lane + k;
-        if (pos < nu) yj[pos].x = a4[k];
-        else if (pos < 2 * nu) yj[pos - nu].y = a4[k];
+        for (int i = 0; i < RU; ++i)
+          if (p + i < p1) {
+            acc.x += v[i].x;
+            acc.y += v[i].y;
+            acc.z += v[i].z;
+            acc.w += v[i].w;
+          }
       }
-    } else {
-      Es4[wave][lane] = acc;
+      if (IDENT) {  // y_j = E_j: this lane's four positions of [Er | Ei]
+        float2* yj = y + (int64_t)r * nb_total + j * nu;
+        const float a4[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int pos = 4 * lane + k;
+          if (pos < nu) yj[pos].x = a4[k];
+          else if (pos < 2 * nu) yj[pos - nu].y = a4[k];
+        }
+      } else {
+        Es4[wave][qr][lane] = acc;
+      }
     }
   }
   if (IDENT) return;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const float* Es = reinterpret_cast<const float*>(Es4[wave]);
   // 16 lanes per column: lane group cs = lane / 16 takes column c0 + cs and
   // lane q = lane % 16 rows q, q + 16, ...; each load instruction reads four
   // whole 128-byte lines of S_j
   constexpr int RQ = (EQ * 4 + 15) / 16;  // rows per lane (N_u <= 4 EQ)
   const int q = lane & 15, cs = lane >> 4;
-  float er[RQ], ei[RQ];
+  float er[RB][RQ], ei[RB][RQ];
 #pragma unroll
-  for (int i = 0; i < RQ; ++i) {
-    const int u = min(q + 16 * i, nu - 1);
-    er[i] = Es[u];
-    ei[i] = Es[nu + u];
+  for (int qr = 0; qr < RB; ++qr) {
+    // vectors past the last one repeat it; their results are not stored
+    const float* Es = reinterpret_cast<const float*>(Es4[wave][min(qr, nr - 1)]);
+#pragma unroll
+    for (int i = 0; i < RQ; ++i) {
+      const int u = min(q + 16 * i, nu - 1);
+      er[qr][i] = Es[u];
+      ei[qr][i] = Es[nu + u];
+    }
   }
   const int64_t start = nb_ptr[j];
   const int64_t nb = nb_ptr[j + 1] - start;
   const float2* Sb = S + start * nu;
-  float2* yb = y + (int64_t)r * nb_total + start;
   for (int64_t c0 = 0; c0 < nb; c0 += 4) {
     const int64_t c = c0 + cs;
     const float2* col = Sb + min(c, nb - 1) * nu;
     float2 sv[RQ];
 #pragma unroll
     for (int i = 0; i < RQ; ++i) sv[i] = col[min(q + 16 * i, nu - 1)];
-    float sr = 0.f, si = 0.f;
 #pragma unroll
-    for (int i = 0; i < RQ; ++i)
-      if (q + 16 * i < nu) {
-        sr = fmaf(sv[i].x, er[i], fmaf(-sv[i].y, ei[i], sr));
-        si = fmaf(sv[i].x, ei[i], fmaf(sv[i].y, er[i], si));
+    for (int qr = 0; qr < RB; ++qr) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int i = 0; i < RQ; ++i)
+        if (q + 16 * i < nu) {
+          sr = fmaf(sv[i].x, er[qr][i], fmaf(-sv[i].y, ei[qr][i], sr));
+          si = fmaf(sv[i].x, ei[qr][i], fmaf(sv[i].y, er[qr][i], si));
+        }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
       }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-      sr += __shfl_xor(sr, o, 64);
-      si += __shfl_xor(si, o, 64);
+      if (qr < nr && c < nb && q == 0)
+        y[(int64_t)(r0 + qr) * nb_total + start + c] = make_float2(sr, si);
     }
-    if (c < nb && q == 0) yb[c] = make_float2(sr, si);
   }
 }
 
@@ -1098,10 +1150,15 @@ int launch_unpack(const Plan& p, const float* P, void* out, int nrhs, void* stre
 int launch_aggregate(const Plan& p, const void* x, float* P, int nrhs, void* stream,
                      const StageEvents* ev) {
   if (!p.has_basis) return launch_pack(p, x, P, nrhs, stream, ev);
-  UBF_LAUNCH(ev, aggregate_kernel, dim3((unsigned)p.n_box, nrhs), dim3(kBlock),
-             (hipStream_t)stream, (const float2*)x, p.d_nb_ptr, (const float2*)p.d_S, P,
-             p.n_box, p.nb_total(), p.nu, p.kh, p.khb, p.fp16() ? 2 : (p.split() ? 1 : 0),
-             p.d_box_scale);
+  // S_i is read once per block of right-hand sides
+  const int mode = p.fp16() ? 2 : (p.split() ? 1 : 0);
+#define UBF_AGG(RB)                                                                        \
+  UBF_LAUNCH(ev, aggregate_kernel<RB>, dim3((unsigned)p.n_box, (nrhs + RB - 1) / RB),      \
+             dim3(kBlock), (hipStream_t)stream, (const float2*)x, p.d_nb_ptr,              \
+             (const float2*)p.d_S, P, p.n_box, p.nb_total(), p.nu, p.kh, p.khb, mode,       \
+             p.d_box_scale, nrhs)
+  if (nrhs == 1) UBF_AGG(1); else if (nrhs == 2) UBF_AGG(2); else UBF_AGG(4);
+#undef UBF_AGG
   return (int)hipGetLastError();
 }
 
@@ -1181,21 +1238,26 @@ int launch_disaggregate(const Plan& p, bool from_parts, const float* part,
   // Larger launches keep four per workgroup: over many rounds the dynamic
   // dispatch balances by itself, and a million one-wavefront workgroups
   // cost a little more to dispatch (1% on the 314,171-box, 4-RHS batch).
-  const int wpg = (int64_t)p.n_box * nrhs <= 8192 ? 1 : kBlock / 64;
-  const dim3 wgrid((unsigned)((p.n_box + wpg - 1) / wpg), nrhs), wblock(64 * wpg);
+  // With T_j = S_j^T a wavefront serves up to four right-hand sides, so
+  // that S_j is read once for them; the identity basis has no S_j to share.
+  const int rb = (mode == 1 && nrhs > 1) ? (nrhs == 2 ? 2 : 4) : 1;
+  const int64_t nrb = (nrhs + rb - 1) / rb;
+  const int wpg = (int64_t)p.n_box * nrb <= 8192 ? 1 : kBlock / 64;
+  const dim3 wgrid((unsigned)((p.n_box + wpg - 1) / wpg), (unsigned)nrb), wblock(64 * wpg);
+#define UBF_WAVE(IDENT, RB)                                                                \
+  UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, IDENT, RB>), wgrid, wblock, s, part,        \
+             p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,     \
+             p.n_box, nb_total, p.nu, p.kh, nrhs)
   if (from_parts && mode == 1 && small && few_rows) {
-    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, false>), wgrid, wblock, s, part,
-               p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
-               p.n_box, nb_total, p.nu, p.kh);
+    if (rb == 1) UBF_WAVE(false, 1); else if (rb == 2) UBF_WAVE(false, 2); else UBF_WAVE(false, 4);
   } else if (from_parts && mode == 0 && small && few_rows) {
-    UBF_LAUNCH(ev, (disaggregate_wave_kernel<21, true>), wgrid, wblock, s, part,
-               p.d_test_ptr, p.n_pairs(), p.d_nb_ptr, (const float2*)p.d_S, (float2*)y,
-               p.n_box, nb_total, p.nu, p.kh);
+    UBF_WAVE(true, 1);
   } else if (from_parts) {
     if (small) UBF_DISAGG(true, 21); else UBF_DISAGG(true, 49);
   } else {
     if (small) UBF_DISAGG(false, 21); else UBF_DISAGG(false, 49);
   }
+#undef UBF_WAVE
 #undef UBF_DISAGG
   return (int)hipGetLastError();
 }

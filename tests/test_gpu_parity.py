@@ -82,6 +82,33 @@ def test_far_mvm_synthetic_basis(explicit_T):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split-fp16"])
+@pytest.mark.parametrize("nrhs", [3, 4, 5, 8])
+def test_basis_rhs_blocks_match_single_vectors(precision, nrhs):
+    # stages 1 and 3 read S once per block of up to four right-hand sides
+    # (3: one partial block; 5: a full block and a block of one); every
+    # vector's result equals the same vector run alone, bit for bit, and the
+    # oracle within the bar
+    w = W.config(1)
+    announce("basis rhs blocks", w.name, precision, "nrhs", nrhs)
+    nb = np.full(w.n_box, 81)
+    nb_ptr, S = W.random_basis(nb, w.n_u, 21)
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=nrhs, precision=precision)
+    ff.set_basis(nb_ptr, to_dev(S))
+    x = W.complex_normal((nrhs, int(nb_ptr[-1])), 22)
+    y = to_host(ff(to_dev(x)))
+    ref = O.far_mvm(x.astype(np.complex128), w.boxes, w.a, w.k, w.n_d, nb_ptr,
+                    S.astype(np.complex128), mode=w.far_mode)
+    for r in range(nrhs):
+        y1 = to_host(ff(to_dev(x[r:r + 1])))
+        assert np.array_equal(y[r:r + 1], y1), f"rhs {r} differs from its single run"
+        err = rel_l2(y[r], ref[r])
+        assert err <= TOL, (r, err)
+    print(f"{precision} nrhs {nrhs}: worst rel_l2 = "
+          f"{max(rel_l2(y[r], ref[r]) for r in range(nrhs)):.3e}")
+    ff.close()
+
+
 def test_ragged_basis_with_empty_boxes():
     boxes = W.grid_boxes(4, 4, 5)
     rng = np.random.default_rng(3)
