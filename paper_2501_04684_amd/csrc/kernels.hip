@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
     const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
     float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row,
-    const float* __restrict__ off_scale, const float* __restrict__ box_scale, int nrhs) {
+    const float* __restrict__ off_scale, const float* __restrict__ box_scale) {
   typedef typename Mfma16<F16>::vec vec16;
   constexpr int KH = (NU + 3) & ~3;      // FP32 half-length (partial rows)
   constexpr int KHB = (NU + 7) & ~7;     // BF16 half-length
@@ -569,10 +569,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
 
   const int group = xcd_chunk(blockIdx.x, gridDim.x);
   const int cbeg = wg_ptr[group], cend = wg_ptr[group + 1];
-  // the workgroup walks items v = chunk * nrhs + rhs over its chunks, every
-  // right-hand side of a chunk in turn, so that a chunk's operator is staged
-  // once for all of them
-  const int vbeg = cbeg * nrhs, vend = cend * nrhs;
+  const int rhs = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
 
@@ -595,15 +592,12 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   const int64_t last = n_pairs - 1;
 
   // As in translate_mfma_kernel: unconditional memory operations, pair
-  // indices two items ahead, B values one item ahead (ring refill).
+  // indices two chunks ahead, B values one chunk ahead (ring refill).
   int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
-  int rhs0 = 0;  // vbeg is the first vector of chunk cbeg
-  const bool has1 = vbeg + 1 < vend;
-  const int c1 = (vbeg + 1) / nrhs;
-  int rhs1 = has1 ? vbeg + 1 - c1 * nrhs : 0;
-  int o1 = has1 ? chunks[4 * c1] : o0;
-  int b1 = has1 ? chunks[4 * c1 + 1] : 0;
-  int n1 = has1 ? chunks[4 * c1 + 2] : 0;
+  const bool has1 = cbeg + 1 < cend;
+  int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
+  int b1 = has1 ? chunks[4 * (cbeg + 1) + 1] : 0;
+  int n1 = has1 ? chunks[4 * (cbeg + 1) + 2] : 0;
   int64_t i0 = min((int64_t)b0 + col0 + r, last), i1 = min((int64_t)b1 + col0 + r, last);
   int src0 = pair_src[i0], dst0 = pair_dst[i0];
   int src1 = pair_src[i1], dst1 = pair_dst[i1];
@@ -611,7 +605,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   // k-step g of a box vector is 64 bytes: hi of both halves, then lo of both
   vec16 bh[NGB], bl[NPROD == 3 ? NGB : 1];
   {
-    const vec16* pv = reinterpret_cast<const vec16*>(P + ((int64_t)rhs0 * n_box + src0) * VSTR);
+    const vec16* pv = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src0) * VSTR);
 #pragma unroll
     for (int g = 0; g < NGB; ++g) {
       bh[g] = pv[4 * g + h];
@@ -619,10 +613,10 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     }
   }
   // FP16: the scale of the current chunk's column (this lane's source box)
-  float bsc0 = F16 ? box_scale[(int64_t)rhs0 * n_box + src0] : 1.f, bsc1 = 1.f;
+  float bsc0 = F16 ? box_scale[(int64_t)rhs * n_box + src0] : 1.f, bsc1 = 1.f;
 
   int staged = -1;
-  for (int v = vbeg; v < vend; ++v) {
+  for (int ch = cbeg; ch < cend; ++ch) {
     if (o0 != staged) {  // uniform across the workgroup
       __syncthreads();
       const uintx4* g4 = reinterpret_cast<const uintx4*>(table + (size_t)o0 * 4 * PLANE);
@@ -637,15 +631,13 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
       __syncthreads();
       staged = o0;
     }
-    const bool has2 = v + 2 < vend;
-    const int c2 = (v + 2) / nrhs;
-    const int rhs2 = has2 ? v + 2 - c2 * nrhs : 0;
-    const int o2 = has2 ? chunks[4 * c2] : o1;
-    const int b2 = has2 ? chunks[4 * c2 + 1] : 0;
-    const int n2 = has2 ? chunks[4 * c2 + 2] : 0;
+    const bool has2 = ch + 2 < cend;
+    const int o2 = has2 ? chunks[4 * (ch + 2)] : o1;
+    const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
+    const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
     const int64_t i2 = min((int64_t)b2 + col0 + r, last);
-    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs1 * n_box + src1) * VSTR);
-    if (F16) bsc1 = box_scale[(int64_t)rhs1 * n_box + src1];
+    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src1) * VSTR);
+    if (F16) bsc1 = box_scale[(int64_t)rhs * n_box + src1];
     int src2, dst2;
 
     if (col0 < n0) {  // wave-uniform
@@ -684,7 +676,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
 
       const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
       float* tile = reinterpret_cast<float*>(tiles4[wave]);
-      float* part_rhs = part + (int64_t)rhs0 * n_pairs * PSTR;
+      float* part_rhs = part + (int64_t)rhs * n_pairs * PSTR;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
         store_block_transposed(tile, acc[rb], sc, dst0, n0 - col0, part_rhs, PSTR, rb * 32);
@@ -697,8 +689,8 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
       src2 = pair_src[i2];
       dst2 = pair_dst[i2];
     }
-    o0 = o1; n0 = n1; dst0 = dst1; rhs0 = rhs1;
-    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2; rhs1 = rhs2;
+    o0 = o1; n0 = n1; dst0 = dst1;
+    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;
     bsc0 = bsc1;
   }
 }
@@ -1180,9 +1172,9 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
   if (p.split()) {
     const unsigned short* tb = reinterpret_cast<const unsigned short*>(p.d_table);
 #define UBF_SPLIT(NU, F16, NPROD)                                                         \
-  UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD>), dim3((unsigned)p.n_groups()),   \
-             dim3(kBlock), s, tb, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P,   \
-             part, p.n_box, p.n_pairs(), trash, p.d_off_scale, p.d_box_scale, nrhs)
+  UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD>), groups, dim3(kBlock), s, tb,      \
+             p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,         \
+             p.n_pairs(), trash, p.d_off_scale, p.d_box_scale)
 #define UBF_SPLIT_NU(F16, NPROD)                           \
   switch (p.nu) {                                          \
     case 81: UBF_SPLIT(81, F16, NPROD); break;             \
