@@ -90,8 +90,10 @@ enum ubf_precision {
 /* Problem statement (Sec. 2: box grid, dipoles per box, wavenumber). */
 typedef struct ubf_problem {
   int64_t n_boxes;         /* number of occupied boxes, >= 1 */
-  const int32_t* box_ijk;  /* host, 3*n_boxes: (x, y, z) per box, each >= 0,
-                              no duplicates; copied at creation */
+  const int32_t* box_ijk;  /* host, 3*n_boxes: (x, y, z) per box, each in
+                              0..2^31-1 (any int32 >= 0; the box index is
+                              keyed on the exact triple), no duplicates;
+                              copied at creation */
   double a;                /* box side, > 0 */
   double k;                /* free-space wavenumber, > 0, per unit of a */
   double eta;              /* intrinsic impedance; 0 selects 376.730313668 */
@@ -308,7 +310,9 @@ int ubf_gmres_start(ubf_gmres* solver, const void* d_b, void* d_x, void* hip_str
 /* Enqueue one Arnoldi step (one product, orthogonalisation, rotation); when
  * the cycle is full, also the restart (x += V y, one more product for the
  * new residual). Never waits. Errors: UBF_ESTATE (not started, finished,
- * plan unbound or basis changed), UBF_EDEVICE. */
+ * plan unbound, basis changed, or the plan bound again with a max_nrhs
+ * below the solver's nrhs), UBF_EDEVICE. All checks finish before any
+ * device work is enqueued. */
 int ubf_gmres_step(ubf_gmres* solver, void* hip_stream);
 
 /* Status of the last enqueued step: with wait = 0 it returns at once
@@ -331,7 +335,9 @@ int ubf_gmres_finish(ubf_gmres* solver, void* hip_stream);
  * (host) receives the square root of the last Rayleigh quotient, which
  * approaches the norm from below. Uses the solver's Krylov blocks, so a
  * solve in progress is abandoned (start again afterwards). Waits for the
- * stream. Errors: UBF_EINVAL, UBF_ESTATE, UBF_EDEVICE. */
+ * stream. Errors: UBF_EINVAL (null, iters out of range, or a plan whose
+ * product is not complex symmetric: an explicit T, or networks standing in
+ * for the operators), UBF_ESTATE, UBF_EDEVICE. */
 int ubf_gmres_norm_estimate(ubf_gmres* solver, int32_t iters, uint64_t seed,
                             void* hip_stream, double* out);
 

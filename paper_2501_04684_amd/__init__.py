@@ -33,7 +33,9 @@ __all__ = [
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 HEADER = os.path.join(ROOT, "include", "ubf.h")
-library_path = os.path.join(HERE, "libubf.so")
+# UBF_LIBRARY may name another build of the same library (the host-sanitizer
+# build); it is loaded exactly like the in-tree one.
+library_path = os.environ.get("UBF_LIBRARY") or os.path.join(HERE, "libubf.so")
 
 FAR_ILIST, FAR_FULL = 0, 1
 FP32, SPLIT_BF16, SPLIT_FP16, FP16 = 0, 1, 2, 3

@@ -36,26 +36,44 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every source and link ``libubf.so``; returns its path."""
+# Host-only sanitizer build (plan builder, C ABI, solver host code): the
+# device code is the same objects as the product library.
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                  "-fno-sanitize-recover=undefined"]
+SANITIZE_LIB = os.path.join(BUILD, "sanitize", "libubf.so")
+
+
+def build(verbose: bool = True, sanitize: bool = False) -> str:
+    """Compile every source and link ``libubf.so``; returns its path.
+
+    ``sanitize=True`` builds the host C++ with AddressSanitizer and
+    UndefinedBehaviorSanitizer into ``_build/sanitize/libubf.so`` instead
+    (load it with ``UBF_LIBRARY`` set to that path and the sanitizer runtime
+    preloaded); the HIP objects are the product's.
+    """
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
-    os.makedirs(BUILD, exist_ok=True)
+    out_dir = os.path.dirname(SANITIZE_LIB) if sanitize else BUILD
+    os.makedirs(out_dir, exist_ok=True)
     objs = []
     for src in HOST_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        obj = os.path.join(out_dir, src + ".o")
+        extra = SANITIZE_FLAGS if sanitize else []
+        _run(["g++", *HOST_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        if not (sanitize and os.path.exists(obj)):
+            _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    lib = SANITIZE_LIB if sanitize else LIB
+    tmp = lib + ".tmp"
+    link_extra = ["-lasan", "-lubsan"] if sanitize else []
     _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs,
-          f"-L{ROCM}/lib", "-lamdhip64", "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+          f"-L{ROCM}/lib", "-lamdhip64", "-lpthread", *link_extra])
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build()
+    build(sanitize="--sanitize" in sys.argv[1:])
     sys.exit(0)

@@ -522,7 +522,9 @@ int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
 
 int ubf_plan_offsets(const ubf_plan* plan, int32_t* out) {
   if (!plan || !out) return fail(UBF_EINVAL, "plan or out is NULL");
-  std::memcpy(out, plan->p.offsets.data(), plan->p.offsets.size() * sizeof(int32_t));
+  // an empty far set has no offsets (and vector::data() may then be null)
+  if (!plan->p.offsets.empty())
+    std::memcpy(out, plan->p.offsets.data(), plan->p.offsets.size() * sizeof(int32_t));
   return ok();
 }
 
@@ -531,6 +533,7 @@ int ubf_plan_far_pairs(const ubf_plan* plan, int32_t* test, int32_t* src,
   if (!plan) return fail(UBF_EINVAL, "plan is NULL");
   const ubf::Plan& p = plan->p;
   const size_t n = p.pair_src.size() * sizeof(int32_t);
+  if (n == 0) return ok();  // vector::data() of an empty far set may be null
   if (test) std::memcpy(test, p.pair_test.data(), n);
   if (src) std::memcpy(src, p.pair_src.data(), n);
   if (offset_index) std::memcpy(offset_index, p.pair_off.data(), n);

@@ -71,10 +71,13 @@ __device__ inline void put_coef(float* Pb, int u, float re, float im, int kh, in
 }
 
 // Power-of-two scale bringing a box vector's largest |Re|, |Im| to
-// [2^14, 2^15) (1 for a zero vector); its inverse is exact.
+// [2^14, 2^15) (1 for a zero vector). The exponent is held at -126 or
+// above, so the scale is a normal float and its inverse (at most 2^126) is
+// finite and exact; a vector whose largest part is below 2^-112 is then
+// scaled up by 2^126 only, which still leaves that part within FP16 range.
 __device__ inline float box_scale_for(float maxabs) {
   if (!(maxabs > 0.f)) return 1.f;
-  return ldexpf(1.f, ilogbf(maxabs) - 14);
+  return ldexpf(1.f, max(ilogbf(maxabs) - 14, -126));
 }
 
 constexpr int kBlock = 256;
@@ -695,48 +698,6 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   }
 }
 
-// Plain translation for box sizes without a matrix-core variant: one
-// workgroup per (chunk, rhs), one thread per output row, operator rows read
-// from the table through the cache.
-__global__ __launch_bounds__(kBlock) void translate_generic_kernel(
-    const float* __restrict__ table, const int32_t* __restrict__ chunks,
-    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
-    const float* __restrict__ P, float* __restrict__ part, int64_t n_box,
-    int64_t n_pairs, int nu, int kh) {
-  __shared__ float pv[2 * 196];
-  const int chunk = blockIdx.x;
-  const int rhs = blockIdx.y;
-  const int o = chunks[4 * chunk];
-  const int begin = chunks[4 * chunk + 1];
-  const int count = chunks[4 * chunk + 2];
-  const size_t plane = (size_t)nu * kh;
-  const float* Gr = table + (size_t)o * 2 * plane;
-  const float* Gi = Gr + plane;
-  const int pstr = 2 * kh;
-  for (int c = 0; c < count; ++c) {
-    const int64_t pos = (int64_t)begin + c;
-    const int src = pair_src[pos];
-    const int64_t dst = pair_dst[pos];
-    __syncthreads();
-    for (int t = threadIdx.x; t < pstr; t += kBlock)
-      pv[t] = P[((int64_t)rhs * n_box + src) * pstr + t];
-    __syncthreads();
-    for (int m = threadIdx.x; m < 2 * nu; m += kBlock) {
-      const bool im = m >= nu;
-      const int rr = im ? m - nu : m;
-      const float* gr = Gr + (size_t)rr * kh;
-      const float* gi = Gi + (size_t)rr * kh;
-      float s = 0.f;
-      if (im) {
-        for (int v = 0; v < nu; ++v) s = fmaf(gi[v], pv[v], fmaf(gr[v], pv[kh + v], s));
-      } else {
-        for (int v = 0; v < nu; ++v) s = fmaf(gr[v], pv[v], fmaf(-gi[v], pv[kh + v], s));
-      }
-      part[((int64_t)rhs * n_pairs + dst) * pstr + m] = s;
-    }
-  }
-}
-
 // ---------------------------------------------------------------- stage 3
 
 // Complex values of S_j staged in LDS per column batch (81 columns of 81,
@@ -1207,9 +1168,9 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
                  p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box, p.n_pairs(), trash);
       break;
     default:
-      UBF_LAUNCH(ev, translate_generic_kernel, dim3((unsigned)nch, nrhs), dim3(kBlock), s,
-                 p.d_table, p.d_chunks, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
-                 p.n_pairs(), p.nu, p.kh);
+      // every N_u of n_d 1..4 has a matrix-core kernel (192 goes to the
+      // staged one); anything else was rejected at plan creation
+      return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
 }

@@ -25,32 +25,45 @@ constexpr double kMaxTableBytes = 16.0 * (1ull << 30);
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Lookup of a box index from integer coordinates.
+// Lookup of a box index from integer coordinates. Small bounding grids use
+// a dense array; larger ones a hash map keyed on the exact coordinate
+// triple (any int32 >= 0 per axis), so distinct boxes never share a key.
 struct BoxIndex {
-  int32_t nx = 0, ny = 0, nz = 0;
+  struct Key {
+    int32_t x, y, z;
+    bool operator==(const Key& o) const { return x == o.x && y == o.y && z == o.z; }
+  };
+  struct KeyHash {
+    size_t operator()(const Key& k) const {
+      uint64_t h = (uint32_t)k.x;
+      h = h * 0x9E3779B97F4A7C15ull ^ (uint32_t)k.y;
+      h = h * 0x9E3779B97F4A7C15ull ^ (uint32_t)k.z;
+      return (size_t)(h ^ (h >> 31));
+    }
+  };
+  int64_t nx = 0, ny = 0, nz = 0;
   std::vector<int32_t> dense;
-  std::unordered_map<uint64_t, int32_t> sparse;
+  std::unordered_map<Key, int32_t, KeyHash> sparse;
   bool use_dense = true;
 
-  static uint64_t key(int64_t x, int64_t y, int64_t z) {
-    return (uint64_t(x) << 42) ^ (uint64_t(y) << 21) ^ uint64_t(z);
-  }
-  // Index boxes b[0..n) (3 coordinates each); false on a duplicate.
+  // Index boxes b[0..n) (3 coordinates each, all >= 0); false on a duplicate.
   bool build(const int32_t* b, int64_t n) {
-    int32_t mx = 0, my = 0, mz = 0;
+    int64_t mx = 0, my = 0, mz = 0;
     for (int64_t i = 0; i < n; ++i) {
-      mx = std::max(mx, b[3 * i]);
-      my = std::max(my, b[3 * i + 1]);
-      mz = std::max(mz, b[3 * i + 2]);
+      mx = std::max<int64_t>(mx, b[3 * i]);
+      my = std::max<int64_t>(my, b[3 * i + 1]);
+      mz = std::max<int64_t>(mz, b[3 * i + 2]);
     }
     nx = mx + 1;
     ny = my + 1;
     nz = mz + 1;
-    use_dense = (int64_t)nx * ny * nz <= kDenseCells;
+    // the product of three extents up to 2^31 overflows int64: test stepwise
+    use_dense = nx <= kDenseCells && ny <= kDenseCells && nz <= kDenseCells &&
+                nx * ny <= kDenseCells && nx * ny * nz <= kDenseCells;
     dense.clear();
     sparse.clear();
     if (use_dense) {
-      dense.assign((size_t)nx * ny * nz, -1);
+      dense.assign((size_t)(nx * ny * nz), -1);
       for (int64_t i = 0; i < n; ++i) {
         int32_t& slot = dense[((size_t)b[3 * i] * ny + b[3 * i + 1]) * nz + b[3 * i + 2]];
         if (slot >= 0) return false;
@@ -59,7 +72,7 @@ struct BoxIndex {
     } else {
       sparse.reserve((size_t)n * 2);
       for (int64_t i = 0; i < n; ++i)
-        if (!sparse.emplace(key(b[3 * i], b[3 * i + 1], b[3 * i + 2]), (int32_t)i).second)
+        if (!sparse.emplace(Key{b[3 * i], b[3 * i + 1], b[3 * i + 2]}, (int32_t)i).second)
           return false;
     }
     return true;
@@ -67,7 +80,7 @@ struct BoxIndex {
   int32_t find(int64_t x, int64_t y, int64_t z) const {
     if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) return -1;
     if (use_dense) return dense[((size_t)x * ny + y) * nz + z];
-    auto it = sparse.find(key(x, y, z));
+    auto it = sparse.find(Key{(int32_t)x, (int32_t)y, (int32_t)z});
     return it == sparse.end() ? -1 : it->second;
   }
 };

@@ -137,6 +137,9 @@ int check_solver(ubf_gmres* s) {
   if (!p.ws) return fail(UBF_ESTATE, "the solver's plan is no longer bound");
   if (p.nb_total() != s->n)
     return fail(UBF_ESTATE, "the plan's basis changed since the solver was created");
+  // a plan bound again with a smaller max_nrhs has no room for R vectors
+  if (s->R > p.max_nrhs)
+    return fail(UBF_ESTATE, "the plan was bound again with max_nrhs below the solver's nrhs");
   return UBF_OK;
 }
 
@@ -328,6 +331,13 @@ int ubf_gmres_norm_estimate(ubf_gmres* s, int32_t iters, uint64_t seed, void* hi
   if (e) return e;
   if (!out) return fail(UBF_EINVAL, "out is NULL");
   if (iters < 1 || iters > 100) return fail(UBF_EINVAL, "iters must be in 1..100");
+  // Z^H Z v is formed as conj(Z conj(Z v)), which needs Z complex symmetric:
+  // T = S^T (or the identity basis) with the operator table. An explicit T
+  // or the networks of Sec. 3 (not linear) give another operator.
+  if (s->plan->p.d_T)
+    return fail(UBF_EINVAL, "norm estimate needs T = S^T; the plan has an explicit T");
+  if (s->plan->p.hidden > 0)
+    return fail(UBF_EINVAL, "norm estimate needs the operator table; the plan uses networks");
   hipStream_t q = (hipStream_t)hip_stream;
   const int64_t n = s->n;
   float2* v = col(s, 0);  // first right-hand-side row of two Krylov blocks

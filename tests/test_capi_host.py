@@ -209,6 +209,81 @@ def test_sparse_coordinates_use_hash_index():
         U.plan_destroy(plan)
 
 
+def _lib_pairs(b, mode):
+    plan = U.plan_create(b, A, K, 1, mode)
+    try:
+        t, s, o = U.plan_far_pairs(plan)
+        offs = U.plan_offsets(plan)
+        return sorted(zip(t.tolist(), s.tolist(), map(tuple, offs[o].tolist())))
+    finally:
+        U.plan_destroy(plan)
+
+
+def _oracle_pairs(b, mode):
+    j, i, w = O.far_pairs(b, mode)
+    return sorted(zip(j.tolist(), i.tolist(), map(tuple, w.tolist())))
+
+
+@pytest.mark.parametrize("boxes", [
+    # z = 2^21 + 2 once shared a packed hash key with (0, 1, 2): a spurious
+    # ILIST pair two million boxes apart
+    [[0, 1, 0], [0, 0, 2**21 + 2], [7, 0, 0]],
+    # z = 2^21 once collided with (0, 1, 0): a false duplicate
+    [[0, 0, 2**21], [0, 1, 0], [5, 0, 0]],
+])
+@pytest.mark.parametrize("mode", ["ilist", "full"])
+def test_far_set_exact_at_large_coordinates(boxes, mode):
+    # Algorithm 2 on boxes whose coordinates exceed 21 bits: the sparse box
+    # index must compare whole coordinates (Sec. 2 box partition)
+    b = np.array(boxes, dtype=np.int32)
+    assert _lib_pairs(b, mode) == _oracle_pairs(b, mode)
+
+
+def _clusters(rng, n_clusters):
+    """Random occupancy of small blocks placed at large, colliding coordinates."""
+    base_choices = [0, 2**21, 2**21 - 2, 2**22, 2**30, 2**31 - 8, 4000]
+    parts, origins = [], []
+    for _ in range(n_clusters):
+        while True:
+            org = np.array([rng.choice(base_choices) for _ in range(3)], dtype=np.int64)
+            org -= org % 2  # even origins keep the ILIST parent rule intact
+            org = np.minimum(org, 2**31 - 8)
+            if all(np.abs(org - o).max() > 8 for o in origins):
+                break
+        origins.append(org)
+        ext = rng.integers(2, 6, size=3)
+        g = np.stack(np.meshgrid(*[np.arange(e) for e in ext], indexing="ij"),
+                     axis=-1).reshape(-1, 3)
+        g = g[rng.random(len(g)) < rng.uniform(0.3, 1.0)]
+        if len(g) == 0:
+            g = np.zeros((1, 3), dtype=np.int64)
+        parts.append((org, g))
+    return parts
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_far_set_random_sparse_geometries(seed):
+    # Seeded clusters at coordinates up to 2^31 - 1 (sparse index path):
+    # ILIST never joins clusters more than three boxes apart, so the oracle
+    # runs per cluster on even-shifted coordinates, which leaves the parent
+    # rule floor(c/2) unchanged; FULL runs the oracle on the whole set.
+    rng = np.random.default_rng(1000 + seed)
+    parts = _clusters(rng, int(rng.integers(2, 5)))
+    b = np.concatenate([org + g for org, g in parts]).astype(np.int64)
+    perm = rng.permutation(len(b))
+    b = b[perm]
+    inv = np.argsort(perm)
+    assert b.max() <= 2**31 - 1
+    ref, start = [], 0
+    for org, g in parts:
+        j, i, w = O.far_pairs(g, "ilist")
+        ref += [(int(inv[start + jj]), int(inv[start + ii]), tuple(ww))
+                for jj, ii, ww in zip(j.tolist(), i.tolist(), w.tolist())]
+        start += len(g)
+    assert _lib_pairs(b.astype(np.int32), "ilist") == sorted(ref)
+    assert _lib_pairs(b.astype(np.int32), "full") == _oracle_pairs(b, "full")
+
+
 def test_split_precision_plan():
     b = W.grid_boxes(4, 4, 4)
     plan = U.plan_create(b, A, K, 3, "ilist", precision="split-bf16")
