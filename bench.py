@@ -53,6 +53,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_mvm_shell3338_hbm_traffic.jso
 # loop: an event costs a few microseconds of device time, about a tenth
 # of a product when all four are recorded on every product.
 PROFILE_EVERY = 8
+# Calls of each latency loop (at least; --steps if larger).
+LATENCY_CALLS = 200
 NETWORK_FILE = os.path.join(ROOT, "paper_2501_04684_amd", "data", "networks_nd4_h50_a0.125.npz")
 # Stage-2 forms: (dtype label, BF16/FP16 products per pair or 0 for FP32)
 FORMS = {"split-bf16": ("f32 (stage 2 bf16 hi/lo x3, f32 accumulation)", 3),
@@ -169,30 +171,43 @@ def parse():
     return args
 
 
-def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
-    """Time the FP64 oracle on the same workload (bounded sample)."""
+def error_stats(errs):
+    import numpy as np
+
+    e = np.asarray(errs, dtype=np.float64)
+    return {"n_vectors": int(len(e)), "median": float(np.median(e)), "max": float(e.max()),
+            "min": float(e.min())}
+
+
+def cpu_baseline(w, nb_ptr, S, X, budget_s, min_vectors=20):
+    """Time the FP64 oracle on the same workload (bounded sample): one call
+    per input vector, cycling through the seeded vectors the GPU ran, for
+    the time budget (and at least ``min_vectors`` vectors). Returns the
+    baseline record and the oracle results per vector (for the error of
+    every vector the oracle ran, Eq. 18)."""
     import numpy as np
     import oracle as O
     from threadpoolctl import threadpool_info
 
     S128 = None if S is None else S.astype(np.complex128)
-    x = x0.astype(np.complex128)
+    refs = []
     t0 = time.perf_counter()
     n = 0
-    y_ref = None
     while True:
-        y = O.far_mvm(x, w.boxes, w.a, w.k, w.n_d, nb_ptr, S128, mode=w.far_mode)
-        if y_ref is None:
-            y_ref = y
+        v = n % len(X)
+        y = O.far_mvm(X[v].astype(np.complex128), w.boxes, w.a, w.k, w.n_d, nb_ptr, S128,
+                      mode=w.far_mode)
+        if n < len(X):
+            refs.append(y)
         n += 1
-        if time.perf_counter() - t0 >= budget_s:
+        if time.perf_counter() - t0 >= budget_s and n >= min(min_vectors, len(X)):
             break
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()
                    if p.get("user_api") == "blas"] or [1])
-    rel = float(np.linalg.norm(y0_gpu - y_ref) / np.linalg.norm(y_ref))
     # the same oracle on one BLAS thread, half the time budget
     from threadpoolctl import threadpool_limits
+    x = X[0].astype(np.complex128)
     with threadpool_limits(limits=1, user_api="blas"):
         t1 = time.perf_counter()
         n1 = 0
@@ -202,22 +217,25 @@ def cpu_baseline(w, nb_ptr, S, x0, y0_gpu, budget_s):
             if time.perf_counter() - t1 >= budget_s / 2:
                 break
         dt1 = time.perf_counter() - t1
-    cpu_model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu_model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
     return {
-        "value": n / dt, "unit": "MVM/s", "cores": int(threads), "kind": "oracle",
-        "sample": f"{n} full far-zone MVMs of the same workload in {dt:.1f} s "
-                  f"(NumPy FP64, grouped by offset; {len(os.sched_getaffinity(0))} "
-                  f"host cores visible, {cpu_model})",
-        "single_thread": {"value": n1 / dt1, "unit": "MVM/s", "cores": 1,
+        "value": n * X.shape[1] / dt, "unit": "MVM/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"{n} full far-zone MVMs of the same workload ({len(refs)} distinct seeded "
+                  f"vectors) in {dt:.1f} s (NumPy FP64, grouped by offset; "
+                  f"{len(os.sched_getaffinity(0))} host cores visible, {cpu_model()})",
+        "single_thread": {"value": n1 * X.shape[1] / dt1, "unit": "MVM/s", "cores": 1,
                           "sample": f"{n1} MVMs in {dt1:.1f} s on one BLAS thread"},
-    }, rel
+    }, refs
+
+
+def vector_errors(Y, refs):
+    """Relative l2 error (Eq. 18) of every (vector, RHS) the oracle ran."""
+    import numpy as np
+
+    errs = []
+    for v, ref in enumerate(refs):
+        for r in range(ref.shape[0]):
+            errs.append(float(np.linalg.norm(Y[v, r] - ref[r]) / np.linalg.norm(ref[r])))
+    return errs
 
 
 def cpu_baseline_networks(w, weights, offsets, x0, y0_net, y0_table, budget_s):
@@ -295,14 +313,15 @@ def bench_networks(args, U, W, torch):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         stage_ms, call_ms = U.profile_end(ff.plan, n_rec)
+        lat = latency_loops(U, torch, ff.plan, X, Y, 1, stream, max(LATENCY_CALLS, args.steps))
         U.far_mvm(ff.plan, X[0], Y, 1, stream)
         torch.cuda.synchronize()
-        return dt, stage_ms / len(call_ms) * 1e3, call_ms, Y.cpu().numpy()
+        return dt, stage_ms / len(call_ms) * 1e3, lat, Y.cpu().numpy()
 
     ff.set_networks(*weights)
-    dt, avg_us, call_ms, y_net = timed()
+    dt, avg_us, lat, y_net = timed()
     ff.set_networks()
-    dt_t, avg_t, call_t, y_table = timed()
+    dt_t, avg_t, lat_t, y_table = timed()
     info = ff.info
     n_pairs, nu = info["n_pairs"], info["n_u"]
     flops = 16.0 * hidden * nu * n_pairs          # two complex layers per pair
@@ -333,8 +352,7 @@ def bench_networks(args, U, W, torch):
                    "translation": "trained networks (first training stage)",
                    "network_test_error_mean": float(np.mean([v["err_mean"]
                                                              for v in orbit.values()]))},
-        "p50_ms": float(np.percentile(call_ms, 50)),
-        "p99_ms": float(np.percentile(call_ms, 99)),
+        **latency_fields(lat),
         "stages": {name: {"avg_us": float(avg_us[i])} for i, name in enumerate(stage_names)},
         "roofline": roof,
         "compare": {"translation": "operator table (FP32 matrix cores, box vectors staged in LDS)",
@@ -440,15 +458,62 @@ def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0):
     dt = time.perf_counter() - t0
     stage_ms, call_ms = U.profile_end(ff.plan, n_rec)
 
-    U.far_mvm(ff.plan, X[0], Y, nrhs, stream)  # first vector, for accuracy
+    lat = latency_loops(U, torch, ff.plan, X, Y, nrhs, stream, max(LATENCY_CALLS, steps))
+
+    # every input vector once more, for the error distribution against the oracle
+    Ys = np.empty((n_vec, nrhs, nb_total), dtype=np.complex64)
+    for v in range(n_vec):
+        U.far_mvm(ff.plan, X[v], Y, nrhs, stream)
+        Ys[v] = Y.cpu().numpy()
     torch.cuda.synchronize()
     out = {"info": ff.info, "plan_ms": plan_ms, "dt": dt, "value": steps * nrhs / dt,
-           "avg_us": stage_ms / len(call_ms) * 1e3, "call_ms": call_ms,
-           "y0": Y.cpu().numpy(), "x0": X[0].cpu().numpy(), "nb_ptr": nb_ptr, "S": S,
-           "nb_total": nb_total}
+           "avg_us": stage_ms / len(call_ms) * 1e3, "call_ms": call_ms, "latency": lat,
+           "Y": Ys, "X": X.cpu().numpy(), "nb_ptr": nb_ptr, "S": S, "nb_total": nb_total}
     ff.close()
     del S_dev
     return out
+
+
+def latency_loops(U, torch, plan, X, Y, nrhs, stream, n_calls):
+    """Per-call latency of the product, apart from the throughput loop.
+
+    device: every one of n_calls back-to-back calls recorded through the
+    kernels' own dispatch events (start of stage 1 to end of stage 3);
+    host: n_calls calls each waited for (launch to completion on the host
+    clock, what a caller that needs the result at once sees)."""
+    import numpy as np
+
+    n_vec = X.shape[0]
+    U.profile_begin(plan, n_calls, 1)
+    for s in range(n_calls):
+        U.far_mvm(plan, X[s % n_vec], Y, nrhs, stream)
+    torch.cuda.synchronize()
+    _, dev_ms = U.profile_end(plan, n_calls)
+    host_ms = np.empty(n_calls)
+    for s in range(n_calls):
+        t0 = time.perf_counter()
+        U.far_mvm(plan, X[s % n_vec], Y, nrhs, stream)
+        torch.cuda.synchronize()
+        host_ms[s] = (time.perf_counter() - t0) * 1e3
+    return {"device_ms": np.asarray(dev_ms, dtype=np.float64), "host_ms": host_ms}
+
+
+def latency_fields(lat):
+    """p50/p99 of both latency loops, with their sample counts."""
+    import numpy as np
+
+    d, h = lat["device_ms"], lat["host_ms"]
+    return {"p50_ms": float(np.percentile(d, 50)), "p99_ms": float(np.percentile(d, 99)),
+            "latency": {"device_calls": int(len(d)),
+                        "device_p50_ms": float(np.percentile(d, 50)),
+                        "device_p99_ms": float(np.percentile(d, 99)),
+                        "device_max_ms": float(d.max()),
+                        "host_sync_calls": int(len(h)),
+                        "host_sync_p50_ms": float(np.percentile(h, 50)),
+                        "host_sync_p99_ms": float(np.percentile(h, 99)),
+                        "what": "device: kernel dispatch events of every call in a "
+                                "back-to-back loop (stage 1 start to stage 3 end); "
+                                "host_sync: each call launched and waited for"}}
 
 
 def batch_form(U, W, torch, w, precision, warmup, steps):
@@ -810,8 +875,7 @@ def main():
                              if S is not None else "identity"),
                    "nrhs": nrhs, "precision": chosen,
                    "translate_groups": info["translate_groups"]},
-        "p50_ms": float(np.percentile(res["call_ms"], 50)),
-        "p99_ms": float(np.percentile(res["call_ms"], 99)),
+        **latency_fields(res["latency"]),
         "plan_ms": res["plan_ms"],
         "stages": stages,
         "roofline": roof,
@@ -821,29 +885,33 @@ def main():
         out["compare"] = {
             "precision": "fp32" if chosen != "fp32" else "split-bf16",
             "value": other["value"], "translate_us": float(ot[1]),
-            "p50_ms": float(np.percentile(other["call_ms"], 50)),
+            "p50_ms": float(np.percentile(other["latency"]["device_ms"], 50)),
+            "p99_ms": float(np.percentile(other["latency"]["device_ms"], 99)),
             "speedup_of_chosen": res["value"] / other["value"],
             "translate_speedup_of_chosen": float(ot[1] / avg_us[1]),
         }
     if not args.no_cpu_baseline:
         if w.far_mode == "full":
-            cb, rel = cpu_baseline_sampled(w, res["nb_ptr"], S, res["x0"], res["y0"],
+            cb, rel = cpu_baseline_sampled(w, res["nb_ptr"], S, res["X"][0], res["Y"][0],
                                            args.cpu_seconds, n_pairs)
+            out["cpu_baseline"] = cb
+            out["rel_l2_vs_oracle_sampled"] = rel
+            if other is not None:
+                _, orel = cpu_baseline_sampled(w, other["nb_ptr"], other["S"], other["X"][0],
+                                               other["Y"][0], args.cpu_seconds, n_pairs)
+                out["compare"]["rel_l2_vs_oracle_sampled"] = orel
         else:
-            cb, rel = cpu_baseline(w, res["nb_ptr"], S, res["x0"], res["y0"], args.cpu_seconds)
-        out["cpu_baseline"] = cb
-        out["rel_l2_vs_oracle" + ("_sampled" if w.far_mode == "full" else "")] = rel
-        if other is not None and w.far_mode == "full":
-            _, orel = cpu_baseline_sampled(w, other["nb_ptr"], other["S"], other["x0"],
-                                           other["y0"], args.cpu_seconds, n_pairs)
-            out["compare"]["rel_l2_vs_oracle_sampled"] = orel
-        elif other is not None:
-            import oracle as O
-            yref = O.far_mvm(other["x0"].astype(np.complex128), w.boxes, w.a, w.k, w.n_d,
-                             other["nb_ptr"], None if other["S"] is None
-                             else other["S"].astype(np.complex128), mode=w.far_mode)
-            out["compare"]["rel_l2_vs_oracle"] = float(
-                np.linalg.norm(other["y0"] - yref) / np.linalg.norm(yref))
+            # the oracle runs each seeded vector once; both forms ran the same
+            # vectors and basis, so its results serve both
+            cb, refs = cpu_baseline(w, res["nb_ptr"], S, res["X"], args.cpu_seconds)
+            out["cpu_baseline"] = cb
+            st = error_stats(vector_errors(res["Y"], refs))
+            out["rel_l2_vs_oracle"] = st["max"]
+            out["rel_l2_vs_oracle_per_vector"] = st
+            if other is not None:
+                ost = error_stats(vector_errors(other["Y"], refs))
+                out["compare"]["rel_l2_vs_oracle"] = ost["max"]
+                out["compare"]["rel_l2_vs_oracle_per_vector"] = ost
     print(json.dumps(out))
     return 0
 

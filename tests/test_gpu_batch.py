@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_util import announce, rel_l2, to_dev, to_host
+from gpu_util import announce, parity, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -51,8 +51,7 @@ def test_small_batch_matches_oracle_and_solo(precision):
     y = to_host(ff(xd))
     for b, sl in _slices(parts, 81):
         ref = O.far_mvm(x[:, sl].astype(np.complex128), b, A, K, 3)
-        err = rel_l2(y[:, sl], ref)
-        assert err <= TOL, (len(b), err)
+        parity(y[:, sl], ref, TOL, boxes=81, label=f"{precision} scatterer of {len(b)} boxes")
         solo = U.FarField(b, A, K, 3, max_nrhs=2, precision=precision)
         ys = to_host(solo(xd[:, sl].contiguous()))
         assert np.array_equal(ys, y[:, sl])
@@ -77,7 +76,7 @@ def test_batch_with_basis_matches_solo():
         S_sub = S[81 * lo:81 * hi]
         ref = O.far_mvm(x[:, lo:hi].astype(np.complex128), b, A, K, 3, sub_ptr,
                         S_sub.astype(np.complex128))
-        assert rel_l2(y[:, lo:hi], ref) <= TOL
+        parity(y[:, lo:hi], ref, TOL, boxes=sub_ptr, label=f"basis scatterer of {len(b)} boxes")
         solo = U.FarField(b, A, K, 3)
         S_dev = to_dev(S_sub)
         solo.set_basis(sub_ptr, S_dev)
@@ -114,7 +113,7 @@ def test_graph_replay_matches_eager():
     assert e.value.status == -4
 
 
-@pytest.mark.parametrize("precision", ["fp32", "split-bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "split-bf16", "split-fp16", "fp16"])
 def test_tune_keeps_results(precision):
     w = W.config(2)
     announce("tune", w.name, precision)
@@ -158,5 +157,4 @@ def test_batch64_full_size_against_solo_and_oracle():
         P = x[:, sl].reshape(4, len(b), 81).astype(np.complex128)
         ref = O.translate(P, b, w.a, w.k, w.n_d, test_boxes=sample)
         got = y[:, sl].reshape(4, len(b), 81)
-        err = rel_l2(got[:, sample], ref[:, sample])
-        assert err <= TOL, (s, err)
+        parity(got[:, sample], ref[:, sample], TOL, boxes=81, label=f"batch64 scatterer {s}")

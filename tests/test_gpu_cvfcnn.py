@@ -17,7 +17,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_util import announce, rel_l2, to_dev, to_host
+from gpu_util import announce, parity, to_dev, to_host
 from oracle import cvfcnn as C
 
 pytestmark = pytest.mark.gpu
@@ -60,10 +60,7 @@ def test_identity_basis_config1(hidden):
     y = to_host(ff(to_dev(x)))
     P = x.reshape(2, w.n_box, w.n_u).astype(np.complex128)
     ref = C.translate_cvfcnn(P, w.boxes, nets, w.far_mode).reshape(2, -1)
-    for r in range(2):
-        err = rel_l2(y[r], ref[r])
-        print(f"hidden {hidden} rhs {r}: rel_l2 = {err:.3e}")
-        assert err <= TOL
+    parity(y, ref, TOL, boxes=w.n_u, label=f"networks hidden {hidden}")
     ff.close()
 
 
@@ -80,9 +77,7 @@ def test_three_stages_synthetic_basis_config1():
     P = O.aggregate(x.astype(np.complex128), nb_ptr, S.astype(np.complex128), w.n_u)
     E = C.translate_cvfcnn(P, w.boxes, nets, w.far_mode)
     ref = O.disaggregate(E, nb_ptr, S.astype(np.complex128))
-    err = rel_l2(y, ref)
-    print(f"three stages: rel_l2 = {err:.3e}")
-    assert err <= TOL
+    parity(y, ref, TOL, boxes=nb_ptr, label="networks, three stages")
     ff.close()
 
 
@@ -98,9 +93,7 @@ def test_nd4_paper_shape(hidden):
         y = to_host(ff(to_dev(x)))
         P = x.reshape(1, len(boxes), 192).astype(np.complex128)
         ref = C.translate_cvfcnn(P, boxes, nets, "ilist").reshape(1, -1)
-        err = rel_l2(y, ref)
-        print(f"n_d=4 {len(boxes)} boxes, hidden {hidden}: rel_l2 = {err:.3e}")
-        assert err <= TOL
+        parity(y, ref, TOL, boxes=192, label=f"networks n_d=4 {len(boxes)} boxes, hidden {hidden}")
         ff.close()
 
 
@@ -131,9 +124,8 @@ def test_nd4_degenerate_and_single_pair(networks):
         else:
             ref = (C.translate_cvfcnn(P, boxes, nets, "ilist") if networks
                    else O.translate(P, boxes, 0.125, k, 4))
-            err = rel_l2(y, ref.reshape(1, -1))
-            print(f"single pair, networks {networks}: rel_l2 = {err:.3e}")
-            assert err <= (TOL if networks else TOL_FP32)
+            parity(y, ref.reshape(1, -1), TOL if networks else TOL_FP32, boxes=192,
+                   label=f"single pair, networks {networks}")
         ff.close()
 
 
@@ -156,9 +148,8 @@ def test_linear_networks_reproduce_operator_table():
     y_net = to_host(ff(xd))
     ref = O.translate(x.reshape(1, len(boxes), 24).astype(np.complex128), boxes, a, k, n_d,
                       "ilist").reshape(1, -1)
-    e_net, e_table = rel_l2(y_net, ref), rel_l2(y_net, y_table)
-    print(f"linear networks: vs oracle {e_net:.3e}, vs operator table {e_table:.3e}")
-    assert e_net <= TOL_FP32 and e_table <= TOL_FP32
+    parity(y_net, ref, TOL_FP32, boxes=24, label="linear networks vs oracle")
+    parity(y_net, y_table, TOL_FP32, boxes=24, label="linear networks vs operator table")
     # back to the operator table: the same result as before, bit for bit
     ff.set_networks()
     assert np.array_equal(to_host(ff(xd)), y_table)
@@ -174,9 +165,7 @@ def test_shell3338_full_size():
     y = to_host(ff(to_dev(x)))
     P = x.reshape(1, w.n_box, w.n_u).astype(np.complex128)
     ref = C.translate_cvfcnn(P, w.boxes, nets, w.far_mode).reshape(1, -1)
-    err = rel_l2(y, ref)
-    print(f"{w.name}: rel_l2 = {err:.3e}")
-    assert err <= TOL
+    parity(y, ref, TOL, boxes=w.n_u, label=f"networks {w.name}")
     ff.close()
 
 
@@ -197,10 +186,7 @@ def test_sphere762_nd4_full_size_trained_networks():
     y = to_host(ff(to_dev(x)))
     P = x.reshape(2, w.n_box, w.n_u).astype(np.complex128)
     ref = C.translate_cvfcnn(P, w.boxes, _nets(offs, *weights), w.far_mode).reshape(2, -1)
-    for r in range(2):
-        err = rel_l2(y[r], ref[r])
-        print(f"{w.name} trained networks rhs {r}: rel_l2 = {err:.3e}")
-        assert err <= TOL
+    parity(y, ref, TOL, boxes=w.n_u, label=f"{w.name} trained networks")
     ff.close()
 
 

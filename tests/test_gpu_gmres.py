@@ -209,3 +209,46 @@ def test_argument_errors():
         U.gmres_poll(s, 1)
     assert e.value.status == -4
     U.gmres_destroy(s)
+
+
+def test_rebind_with_smaller_max_nrhs_is_refused_before_launch():
+    # a solver for 2 right-hand sides whose plan is bound again for 1: the
+    # plan's workspace no longer holds 2 vectors, so every solver call that
+    # would run a product returns UBF_ESTATE before enqueuing anything
+    boxes = W.grid_boxes(4, 4, 4)
+    announce("gmres rebind smaller max_nrhs")
+    ff = U.FarField(boxes, A_SIDE, K, 3, max_nrhs=2)
+    sol = U.Solver(ff, 1.0 + 1.0j, nrhs=2, restart=5)
+    b = to_dev(W.complex_normal((2, ff.nb_total), 3))
+    x = torch.empty_like(b)
+    sol.start(b, x)
+    sol.poll(wait=True)
+    small = torch.empty(U.workspace_bytes(ff.plan, 1) + 256, dtype=torch.uint8, device="cuda")
+    addr = (small.data_ptr() + 255) & ~255
+    U._check(U.lib().ubf_plan_bind(ff.plan, addr, U.workspace_bytes(ff.plan, 1), 1, None),
+             "ubf_plan_bind")
+    ff.workspace, ff.max_nrhs = small, 1
+    for call in (sol.step, sol.finish, lambda: sol.norm_estimate(1)):
+        with pytest.raises(U.UbfError) as e:
+            call()
+        assert e.value.status == -4 and "max_nrhs" in str(e.value)
+    torch.cuda.synchronize()
+    sol.close()
+    ff.close()
+
+
+def test_norm_estimate_rejects_explicit_T():
+    boxes = W.grid_boxes(4, 4, 4)
+    announce("gmres norm estimate with explicit T")
+    nb = np.full(len(boxes), 30)
+    nb_ptr, S = W.random_basis(nb, 81, 5)
+    T = W.random_basis(nb, 81, 6)[1]
+    ff = U.FarField(boxes, A_SIDE, K, 3)
+    Sd, Td = to_dev(S), to_dev(T)
+    ff.set_basis(nb_ptr, Sd, Td)
+    sol = U.Solver(ff, 1.0, nrhs=1, restart=5)
+    with pytest.raises(U.UbfError) as e:
+        sol.norm_estimate(2)
+    assert e.value.status == -1 and "explicit T" in str(e.value)
+    sol.close()
+    ff.close()

@@ -4,18 +4,26 @@ The paper states no precision; the bar for split precision is a relative
 l2 error <= 1e-3. BF16 hi/lo splits are exact to about 2^-16 relative and
 FP16 hi/lo splits (with power-of-two scaling) to about 2^-22, so both
 three-product forms are held to the 1e-4 of the plain FP32 path. The
-single FP16 product (about 2^-11 per product) is held to 1e-3.
+single FP16 product (about 2^-11 per product) is held to 1e-3. Each bar
+holds over the whole result and element by element (max norm); per test box
+the three-product forms keep the same bar, while the single FP16 product is
+held to 3e-3 per box: its per-product error (2^-11 = 4.9e-4) is already half
+the bar, and a box whose output partly cancels, or whose basis block maps
+the error onto a larger direction than the field, shows a few times the
+whole-result error (measured worst box on the shell: 4.3x).
 """
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
-from gpu_util import announce, rel_l2, to_dev, to_host
+from gpu_util import announce, parity, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
 FORMS = [("split-bf16", 1e-4), ("split-fp16", 1e-4), ("fp16", 1e-3)]
+# per-test-box bar of each form (see the module docstring)
+BOX_TOL = {"split-bf16": 1e-4, "split-fp16": 1e-4, "fp16": 3e-3}
 
 torch = pytest.importorskip("torch")
 U = pytest.importorskip("paper_2501_04684_amd")
@@ -45,9 +53,7 @@ def test_split_translate_parity(cfg, form, tol):
     U.translate(ff.plan, Pd, Ed, 1)
     E = to_host(Ed)
     ref = O.translate(P.astype(np.complex128), w.boxes, w.a, w.k, w.n_d)
-    err = rel_l2(E, ref)
-    print(f"{w.name} {form}: translate rel_l2 = {err:.3e}")
-    assert err <= tol
+    parity(E, ref, tol, boxes=w.n_u, label=f"{w.name} {form} translate", box_tol=BOX_TOL[form])
 
 
 @pytest.mark.parametrize("form,tol", FORMS)
@@ -62,10 +68,7 @@ def test_split_three_stage_shell_and_nrhs(form, tol):
     y = to_host(ff(to_dev(x)))
     ref = O.far_mvm(x.astype(np.complex128), w.boxes, w.a, w.k, w.n_d, nb_ptr,
                     S.astype(np.complex128))
-    for r in range(2):
-        err = rel_l2(y[r], ref[r])
-        print(f"{form} three-stage rhs {r}: rel_l2 = {err:.3e}")
-        assert err <= tol
+    parity(y, ref, tol, boxes=nb_ptr, label=f"{form} three-stage shell", box_tol=BOX_TOL[form])
 
 
 @pytest.mark.parametrize("form,tol", FORMS)
@@ -82,7 +85,8 @@ def test_split_other_cases(n_d, boxes, a, form, tol):
     Ed = torch.empty_like(Pd)
     U.translate(ff.plan, Pd, Ed, 1)
     ref = O.translate(P.astype(np.complex128), boxes, a, 2 * np.pi, n_d)
-    assert rel_l2(to_host(Ed), ref) <= tol
+    parity(to_host(Ed), ref, tol, boxes=3 * n_d ** 3, label=f"{form} n_d {n_d} a {a:g}",
+           box_tol=BOX_TOL[form])
 
 
 @pytest.mark.parametrize("form,tol", FORMS)
@@ -96,24 +100,40 @@ def test_split_deterministic_and_degenerate(form, tol):
     assert not np.any(to_host(one(to_dev(W.complex_normal((1, 81), 1)))))
 
 
+def contribution_scale(P, boxes, a, k, n_d):
+    """Per test box j: sum over its far pairs of ||G_w P_i|| (FP64, the
+    oracle's far set and operators), the size of the terms its sum adds."""
+    j, i, off = O.far_pairs(boxes)
+    uniq, oid = O.offset_ids(off)
+    out = np.zeros((P.shape[0], len(boxes)))
+    for o, w in enumerate(uniq):
+        sel = oid == o
+        G = O.translation_operator(w, a, k, n_d)
+        c = np.einsum("uv,rpv->rpu", G, P[:, i[sel]].astype(np.complex128))
+        np.add.at(out, (slice(None), j[sel]), np.linalg.norm(c, axis=2))
+    return out
+
+
 @pytest.mark.parametrize("form,tol", FORMS)
 def test_wide_dynamic_range_across_boxes(form, tol):
-    """Box vectors spanning 10^+-6: the FP16 forms scale each box vector by
-    its own power of two, so the error stays relative per contribution."""
+    """Box vectors spanning 10^+-6. Each product G_w P_i carries the form's
+    relative error on its own scale (the FP16 forms scale each box vector by
+    its own power of two), and a test box's sum mixes terms of very different
+    sizes, so the per-box bound is the bar times the sum of the norms of the
+    terms the box receives; the whole result is held to the plain bar."""
     w = W.config(1)
     announce("dynamic range", w.name, form)
     ff = split_field(w, form=form)
     P = w.coefficients().reshape(1, w.n_box, w.n_u)
     mag = 10.0 ** np.random.default_rng(12).uniform(-6, 6, w.n_box)
+    # two boxes at the bottom of the FP32 range: their scales clamp at 2^-126
+    mag[[5, 100]] = 1e-36
     P = (P * mag[None, :, None]).astype(np.complex64)
     Pd = to_dev(P)
     Ed = torch.empty_like(Pd)
     U.translate(ff.plan, Pd, Ed, 1)
     E = to_host(Ed)
     ref = O.translate(P.astype(np.complex128), w.boxes, w.a, w.k, w.n_d)
-    # per test box, relative to that box's own field (the sums mix scales)
-    num = np.linalg.norm(E - ref, axis=2)
-    den = np.linalg.norm(ref, axis=2)
-    worst = float((num / den).max())
-    print(f"{form}: worst per-box rel err {worst:.2e}")
-    assert worst <= 30 * tol
+    scale = contribution_scale(P, w.boxes, w.a, w.k, w.n_d)[0]
+    parity(E, ref, tol, boxes=w.n_u, box_scale=scale, label=f"{form} dynamic range",
+           box_tol=tol)
