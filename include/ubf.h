@@ -222,6 +222,28 @@ int ubf_plan_set_networks(ubf_plan* plan, int32_t hidden, const void* d_W1, cons
 int ubf_far_mvm(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs,
                 void* hip_stream);
 
+/* Size of the static device array behind ubf_far_mvm_noalloc (96 MiB). */
+#define UBF_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as ubf_far_mvm, same arguments, kernels and results bit for bit,
+ * but its per-call intermediates (box vectors, partial rows, FP16 box
+ * scales) live in one static device array of UBF_NOALLOC_SCRATCH_BYTES
+ * inside the library instead of the plan's bound workspace (which still
+ * holds the plan's tables). Nothing is allocated on any call; each GPU the
+ * library runs on holds its own copy of the array until the process ends.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (any plan, any stream) race, so
+ * order them on one stream or synchronize between them. The first call on
+ * a device looks the array's address up once.
+ * Errors: those of ubf_far_mvm, plus UBF_EINVAL when one call of nrhs
+ * vectors needs more than UBF_NOALLOC_SCRATCH_BYTES (the 3,338-box shell
+ * with 108,888 far pairs needs 75.6 MB per right-hand side), checked
+ * before any device work. */
+int ubf_far_mvm_noalloc(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs,
+                        void* hip_stream);
+
 /* Record the whole product y = T G S x for these d_x, d_y and nrhs as a
  * HIP graph owned by the plan (the three stage launches, no memory
  * operations), replacing any earlier one. Nothing runs at capture; the

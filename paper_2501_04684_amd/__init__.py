@@ -22,7 +22,8 @@ __all__ = [
     "library_path",
     "declared_symbols", "plan_create", "plan_create_batch", "workspace_bytes",
     "plan_bind", "plan_capture", "plan_replay", "plan_tune",
-    "plan_set_basis", "network_bytes", "plan_set_networks", "far_mvm", "aggregate", "translate", "disaggregate",
+    "plan_set_basis", "network_bytes", "plan_set_networks", "far_mvm", "far_mvm_noalloc",
+    "aggregate", "translate", "disaggregate",
     "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
     "profile_begin", "profile_end", "plan_destroy", "status_string",
     "last_error", "FarField", "gmres_workspace_bytes", "gmres_create", "gmres_start",
@@ -90,6 +91,7 @@ _SIGS = {
     "ubf_network_bytes": (_SZ, [_VP, _I32]),
     "ubf_plan_set_networks": (ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "ubf_far_mvm": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
+    "ubf_far_mvm_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
     "ubf_plan_capture": (ctypes.c_int, [_VP, _VP, _VP, _I32]),
     "ubf_plan_replay": (ctypes.c_int, [_VP, _VP]),
     "ubf_plan_tune": (ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
@@ -258,6 +260,11 @@ def _nrhs(x, nrhs):
 def far_mvm(plan, x, y, nrhs=None, stream=None):
     _check(lib().ubf_far_mvm(plan, _dev_ptr(x), _dev_ptr(y), _nrhs(x, nrhs),
                              _stream(stream)), "ubf_far_mvm")
+
+
+def far_mvm_noalloc(plan, x, y, nrhs=None, stream=None):
+    _check(lib().ubf_far_mvm_noalloc(plan, _dev_ptr(x), _dev_ptr(y), _nrhs(x, nrhs),
+                                     _stream(stream)), "ubf_far_mvm_noalloc")
 
 
 def plan_capture(plan, x, y, nrhs=None):

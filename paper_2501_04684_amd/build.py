@@ -20,7 +20,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["plan.cpp", "capi.cpp", "solver.cpp"]
-HIP_SOURCES = ["kernels.hip", "gmres.hip", "networks.hip"]
+HIP_SOURCES = ["kernels.hip", "gmres.hip", "networks.hip", "noalloc.hip"]
 
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-pthread", "-Wall", "-Wextra",
               "-Wno-unused-parameter", "-D__HIP_PLATFORM_AMD__",

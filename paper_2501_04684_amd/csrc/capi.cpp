@@ -67,16 +67,15 @@ using ubf::fail;
 using ubf::hip_fail;
 using ubf::ok;
 
-
-
-
-
-
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
   const char* pb = (const char*)b;
   return pa < pb + nb && pb < pa + na;
 }
+
+}  // namespace
+
+namespace ubf {
 
 // Common checks of the compute entry points.
 int check_call(ubf_plan* plan, const void* in, void* out, int32_t nrhs,
@@ -92,12 +91,19 @@ int check_call(ubf_plan* plan, const void* in, void* out, int32_t nrhs,
   return UBF_OK;
 }
 
-size_t box_vec_bytes(const ubf::Plan& p, int32_t nrhs) {
-  return (size_t)nrhs * p.n_box * p.nu * 8;
-}
-
 size_t basis_vec_bytes(const ubf::Plan& p, int32_t nrhs) {
   return (size_t)nrhs * p.nb_total() * 8;
+}
+
+}  // namespace ubf
+
+namespace {
+
+using ubf::basis_vec_bytes;
+using ubf::check_call;
+
+size_t box_vec_bytes(const ubf::Plan& p, int32_t nrhs) {
+  return (size_t)nrhs * p.n_box * p.nu * 8;
 }
 
 // Shared body of ubf_plan_create and ubf_plan_create_batch.

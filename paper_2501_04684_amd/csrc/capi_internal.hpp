@@ -51,6 +51,14 @@ int ok();
 int hip_fail(int err, const char* what);
 const std::string& last_error_text();
 
+// Argument checks shared by the compute entry points (null pointers, an
+// unbound plan, nrhs outside 1..max_nrhs, overlapping input and output);
+// nothing touches a device.
+int check_call(ubf_plan* plan, const void* in, void* out, int32_t nrhs, size_t in_bytes,
+               size_t out_bytes);
+// Bytes of [nrhs][sum N_b] complex64 (the product's x and y).
+size_t basis_vec_bytes(const Plan& p, int32_t nrhs);
+
 // The three stages of the product y = T G S x, enqueued on `s`
 // (ev: optional timing events, a start and a stop per stage).
 int enqueue_mvm(const Plan& p, const void* d_x, void* d_y, int32_t nrhs, hipStream_t s,

@@ -333,6 +333,21 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   return L;
 }
 
+ScratchLayout scratch_layout(const Plan& p, int32_t nrhs) {
+  ScratchLayout L{};
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t here = at;
+    at = align256(at + bytes);
+    return here;
+  };
+  L.P = take((size_t)nrhs * p.n_box * p.vstride() * sizeof(float));
+  L.part = take(((size_t)nrhs * p.n_pairs() + 1) * p.pstride() * sizeof(float));
+  L.box_scale = take((size_t)nrhs * p.n_box * sizeof(float));
+  L.total = at;
+  return L;
+}
+
 std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
                        double k, double eta, int n_d, int far_mode,
                        int precision, const int64_t* scat_ptr, int64_t n_scat,

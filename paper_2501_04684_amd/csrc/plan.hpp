@@ -199,6 +199,14 @@ struct Layout {
 };
 Layout workspace_layout(const Plan& p, int32_t max_nrhs);
 
+// The per-call intermediates of one product of nrhs right-hand sides (box
+// vectors, partial rows with their spare row, FP16 box scales), laid out
+// from offset 0 of a scratch region, in bytes.
+struct ScratchLayout {
+  size_t P, part, box_scale, total;
+};
+ScratchLayout scratch_layout(const Plan& p, int32_t nrhs);
+
 // Validate and build; returns an empty string on success, else the reason.
 // scat_ptr (n_scat + 1 prefix offsets into the boxes) splits the boxes into
 // independent scatterers; NULL means one scatterer.
