@@ -532,6 +532,46 @@ struct Mfma16<true> {
   }
 };
 
+// Waits until at most N vector-memory operations of this wavefront are
+// outstanding (vmcnt; expcnt and lgkmcnt left unconstrained).
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Workgroup barrier once every wavefront's LDS reads have returned (so LDS
+// may be overwritten afterwards). Unlike __syncthreads it does not wait for
+// outstanding global loads and stores.
+__device__ inline void lds_reads_done_barrier() {
+  __builtin_amdgcn_s_waitcnt((0xF) | (0x3 << 14) | (0x7 << 4) | (0x0 << 8));  // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+}
+
+// Workgroup barrier after each wavefront has waited for its own direct
+// copies into LDS (wait_vmcnt): LDS reads after it see every wavefront's
+// copied data.
+__device__ inline void lds_copies_done_barrier() {
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Direct copy of N16 16-byte units from global memory into LDS (no
+// registers): round `it` of the workgroup copies units it*kBlock + t, and
+// wavefront w's 64 lanes fill the 1 KB at dst + it*kBlock + 64 w (the
+// copy's LDS address is the wavefront's base plus 16 bytes per lane). `dst`
+// holds ceil(N16 / kBlock) * kBlock units; lanes past N16 read the last
+// unit into padding. Issues ceil(N16 / kBlock) loads per thread.
+template <int N16>
+__device__ inline void copy_to_lds(const uintx4* __restrict__ src, uintx4* dst) {
+  const int t = threadIdx.x, wave = t >> 6;
+#pragma unroll
+  for (int it = 0; it < (N16 + kBlock - 1) / kBlock; ++it)
+    __builtin_amdgcn_global_load_lds(
+        reinterpret_cast<const void*>(src + min(t + it * kBlock, N16 - 1)),
+        (__attribute__((address_space(3))) void*)(dst + it * kBlock + wave * 64), 16, 0, 0);
+}
+
 // Split-precision translation on the 16-bit matrix cores
 // (v_mfma_f32_32x32x16_bf16 / _f16, FP32 accumulation). With G = Gh + Gl
 // and P = Ph + Pl (h = the value rounded to 16 bits, l = the remainder
@@ -541,13 +581,23 @@ struct Mfma16<true> {
 // (about 2^-11 in FP16). In FP16 the operator is stored divided by a
 // power of two per offset and each box vector by a power of two per box
 // and RHS; a column's FP32 result is multiplied back by both (exact).
-// Work layout, pipelining and stores are those of translate_mfma_kernel:
-// lane l owns column l % 32 and K half h = l / 32; a k-step covers 8
-// consecutive values of each half (KHB = NU rounded up to 8, zero padded),
-// read as one 16-byte value per lane from the box vector's 64-byte k-step
-// group (the two lanes of a column read adjacent 16 bytes); the operator's four planes (re.hi,
-// re.lo, im.hi, im.lo) sit in LDS and -Gi is a sign flip. 32-row blocks
+//
+// Work layout as in translate_mfma_kernel: each workgroup walks a range of
+// chunks (up to 128 pairs of one offset); lane l owns column l % 32 and K
+// half h = l / 32; a k-step covers 8 consecutive values of each half (KHB =
+// NU rounded up to 8, zero padded), read as one 16-byte value per lane from
+// the box vector's 64-byte k-step group (the two lanes of a column read
+// adjacent 16 bytes); -Gi is a sign flip of the A values; 32-row blocks
 // cover all 2*NU rows (padding rows read row 0 and are not stored).
+//
+// The operator's planes are stored hi half first ([re.hi | im.hi] then
+// [re.lo | im.lo]) and copied straight into LDS. The hi half is waited for
+// first: pass 1 runs Gh Ph and Gh Pl over all k-steps while the lo half is
+// still arriving, pass 2 runs Gl Ph (and refills the registers with the next
+// chunk's columns). Partial rows leave through a per-wavefront LDS tile:
+// each block is written as 4-row pieces per column, read back as 8 columns
+// x 128 contiguous bytes per store instruction, the destination rows taken
+// once per chunk from their owner lanes.
 template <int NU, bool F16, int NPROD>
 __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const unsigned short* __restrict__ table, const int32_t* __restrict__ chunks,
@@ -557,16 +607,18 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const float* __restrict__ off_scale, const float* __restrict__ box_scale) {
   typedef typename Mfma16<F16>::vec vec16;
   constexpr int KH = (NU + 3) & ~3;      // FP32 half-length (partial rows)
-  constexpr int KHB = (NU + 7) & ~7;     // BF16 half-length
-  constexpr int PLANE = NU * KHB;        // BF16 values per plane
+  constexpr int KHB = (NU + 7) & ~7;     // 16-bit half-length
+  constexpr int PLANE = NU * KHB;        // 16-bit values per plane
   constexpr int M = 2 * NU;
   constexpr int RB = (M + 31) / 32;
   constexpr int NGB = KHB / 8;           // k-steps per half
   constexpr int PSTR = 2 * KH;           // partial row (floats)
   constexpr int VSTR = 2 * KHB;          // box vector (floats)
-  constexpr int N4 = 4 * PLANE * 2 / 16; // 16-byte units per operator
-  constexpr int LD = (N4 + kBlock - 1) / kBlock;
-  __shared__ uintx4 lds4[N4];
+  constexpr int H16 = 2 * PLANE * 2 / 16;                       // 16-byte units per half
+  constexpr int HPAD = (H16 + kBlock - 1) / kBlock * kBlock;    // LDS units per half
+  constexpr int NLD = HPAD / kBlock;     // copies per thread per half
+  constexpr int LO = HPAD * 8;           // lo half, in 16-bit values from the LDS start
+  __shared__ uintx4 lds4[(NPROD == 3 ? 2 : 1) * HPAD];
   __shared__ floatx4 tiles4[4][32 * kTilePitch / 4];  // one per wavefront
   const unsigned short* lds = reinterpret_cast<const unsigned short*>(lds4);
 
@@ -577,7 +629,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   const int r = lane & 31, h = lane >> 5;
 
   // Operator rows of this lane per block: Er rows read re (h = 0) or -im
-  // (h = 1); Ei rows read im (h = 0) or re (h = 1). hi plane = 2c, lo = 2c+1.
+  // (h = 1); Ei rows read im (h = 0) or re (h = 1). Plane c = 0 re, 1 im.
   int abase[RB];
   unsigned asgn[RB];
 #pragma unroll
@@ -586,7 +638,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const bool er = row < NU;
     const int rr = er ? row : (row < M ? row - NU : 0);
     const int c = er ? (h == 1 ? 1 : 0) : (row < M && h == 0 ? 1 : 0);
-    abase[rb] = 2 * c * PLANE + rr * KHB;
+    abase[rb] = c * PLANE + rr * KHB;
     asgn[rb] = (er && h == 1) ? 0x80008000u : 0u;
   }
 
@@ -594,8 +646,8 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   const int col0 = wave * 32;
   const int64_t last = n_pairs - 1;
 
-  // As in translate_mfma_kernel: unconditional memory operations, pair
-  // indices two chunks ahead, B values one chunk ahead (ring refill).
+  // Unconditional memory operations, pair indices two chunks ahead, B
+  // values one chunk ahead (refilled in pass 2).
   int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
   const bool has1 = cbeg + 1 < cend;
   int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
@@ -620,17 +672,22 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
 
   int staged = -1;
   for (int ch = cbeg; ch < cend; ++ch) {
-    if (o0 != staged) {  // uniform across the workgroup
-      __syncthreads();
+    const bool restage = o0 != staged;  // uniform across the workgroup
+    if (restage) {
+      // both halves through registers: the hi half's units, then the lo half's
+      constexpr int NH = NPROD == 3 ? 2 : 1;
       const uintx4* g4 = reinterpret_cast<const uintx4*>(table + (size_t)o0 * 4 * PLANE);
-      uintx4 tmp[LD];
+      uintx4 tmp[NH * NLD];
 #pragma unroll
-      for (int it = 0; it < LD; ++it) tmp[it] = g4[min((int)threadIdx.x + it * kBlock, N4 - 1)];
+      for (int hh = 0; hh < NH; ++hh)
 #pragma unroll
-      for (int it = 0; it < LD; ++it) {
-        const int i = threadIdx.x + it * kBlock;
-        if (i < N4) lds4[i] = tmp[it];
-      }
+        for (int it = 0; it < NLD; ++it)
+          tmp[hh * NLD + it] = g4[hh * H16 + min((int)threadIdx.x + it * kBlock, H16 - 1)];
+      __syncthreads();  // every wavefront is done with the previous operator
+#pragma unroll
+      for (int hh = 0; hh < NH; ++hh)
+#pragma unroll
+        for (int it = 0; it < NLD; ++it) lds4[hh * HPAD + threadIdx.x + it * kBlock] = tmp[hh * NLD + it];
       __syncthreads();
       staged = o0;
     }
@@ -639,58 +696,94 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
     const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
     const int64_t i2 = min((int64_t)b2 + col0 + r, last);
-    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src1) * VSTR);
-    if (F16) bsc1 = box_scale[(int64_t)rhs * n_box + src1];
-    int src2, dst2;
+    const bool active = col0 < n0;  // wave-uniform
 
-    if (col0 < n0) {  // wave-uniform
-      floatx16 acc[RB];
+    floatx16 acc[RB];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+    if (active) {
+      // pass 1: Gh Ph (+ Gh Pl)
 #pragma unroll
       for (int g = 0; g < NGB; ++g) {
-        vec16 a_h[RB], a_l[NPROD == 3 ? RB : 1];
+        vec16 a_h[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           uintx4 ah = *reinterpret_cast<const uintx4*>(lds + abase[rb] + 8 * g);
           ah ^= asgn[rb];
           a_h[rb] = __builtin_bit_cast(vec16, ah);
-          if (NPROD == 3) {
-            uintx4 al = *reinterpret_cast<const uintx4*>(lds + abase[rb] + PLANE + 8 * g);
-            al ^= asgn[rb];
-            a_l[rb] = __builtin_bit_cast(vec16, al);
-          }
         }
-        // consecutive MFMAs go to different row blocks (independent
-        // accumulators); each block's products are RB issues apart
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_h[rb], bh[g], acc[rb]);
         if (NPROD == 3) {
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_h[rb], bl[g], acc[rb]);
+        }
+      }
+    }
+    // the next chunk's column (its index arrived long ago): its box vector
+    // is fetched in pass 2, its FP16 scale here
+    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src1) * VSTR);
+    if (F16) bsc1 = box_scale[(int64_t)rhs * n_box + src1];
+    if (active) {
+      // pass 2: Gl Ph, refilling the registers with the next chunk's columns
+#pragma unroll
+      for (int g = 0; g < NGB; ++g) {
+        if (NPROD == 3) {
+          vec16 a_l[RB];
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            uintx4 al = *reinterpret_cast<const uintx4*>(lds + LO + abase[rb] + 8 * g);
+            al ^= asgn[rb];
+            a_l[rb] = __builtin_bit_cast(vec16, al);
+          }
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_l[rb], bh[g], acc[rb]);
+          bl[g] = pv1[4 * g + 2 + h];
         }
-        bh[g] = pv1[4 * g + h];  // next chunk
-        if (NPROD == 3) bl[g] = pv1[4 * g + 2 + h];
+        bh[g] = pv1[4 * g + h];
       }
-      src2 = pair_src[i2];
-      dst2 = pair_dst[i2];
-
-      const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
-      float* tile = reinterpret_cast<float*>(tiles4[wave]);
-      float* part_rhs = part + (int64_t)rhs * n_pairs * PSTR;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-        store_block_transposed(tile, acc[rb], sc, dst0, n0 - col0, part_rhs, PSTR, rb * 32);
     } else {  // no column of this chunk for this wavefront: fetch the next
 #pragma unroll
       for (int g = 0; g < NGB; ++g) {
         bh[g] = pv1[4 * g + h];
         if (NPROD == 3) bl[g] = pv1[4 * g + 2 + h];
       }
-      src2 = pair_src[i2];
-      dst2 = pair_dst[i2];
+    }
+    const int src2 = pair_src[i2];
+    const int dst2 = pair_dst[i2];
+
+    if (active) {
+      const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
+      float* tile = reinterpret_cast<float*>(tiles4[wave]);
+      float* part_rhs = part + (int64_t)rhs * n_pairs * PSTR;
+      const int seg = lane & 7;
+      // destination row of the columns this lane stores (c = lane/8 + 8 it)
+      int64_t rowoff[4];
+      bool cok[4];
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int c = (lane >> 3) + 8 * it;
+        rowoff[it] = (int64_t)__shfl(dst0, c, 64) * PSTR;
+        cok[it] = c < n0 - col0;
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+          *reinterpret_cast<floatx4*>(tile + r * kTilePitch + 8 * q4 + 4 * h) =
+              floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                      acc[rb][4 * q4 + 3]} * sc;
+        floatx4 v[4];
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+          v[it] = *reinterpret_cast<const floatx4*>(tile + ((lane >> 3) + 8 * it) * kTilePitch +
+                                                    4 * seg);
+        const int m = rb * 32 + 4 * seg;
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+          if (cok[it] && m + 4 <= PSTR)
+            *reinterpret_cast<floatx4*>(part_rhs + rowoff[it] + m) = v[it];
+      }
     }
     o0 = o1; n0 = n1; dst0 = dst1;
     o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;

@@ -93,7 +93,7 @@ int64_t floordiv2(int64_t c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
 
 // One offset's operator image in the table layout. FP32: planes re, im of
 // nu rows of kh floats. Split: G is rounded to FP32 first (as in the FP32
-// path), then hi = bf16(G), lo = bf16(G - hi); planes re.hi, re.lo, im.hi,
+// path), then hi = bf16(G), lo = bf16(G - hi); planes re.hi, im.hi, re.lo,
 // im.lo of nu rows of khb values. Padding columns are zero.
 void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<double>>& G,
                   char* dst, float* scale) {
@@ -117,8 +117,8 @@ void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<doub
         for (int c = 0; c < 2; ++c) {
           const uint16_t hi = fp16_bits(parts[c]);
           const uint16_t lo = fp16_bits(parts[c] - fp16_value(hi));
-          base[(2 * c) * plane + (size_t)u * P.khb + v] = hi;
-          base[(2 * c + 1) * plane + (size_t)u * P.khb + v] = lo;
+          base[c * plane + (size_t)u * P.khb + v] = hi;
+          base[(2 + c) * plane + (size_t)u * P.khb + v] = lo;
         }
       }
     return;
@@ -166,8 +166,8 @@ void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<doub
         for (int c = 0; c < 2; ++c) {
           const uint16_t hi = bf16_bits(parts[c]);
           const uint16_t lo = bf16_bits(parts[c] - bf16_value(hi));
-          base[(2 * c) * plane + (size_t)u * P.khb + v] = hi;
-          base[(2 * c + 1) * plane + (size_t)u * P.khb + v] = lo;
+          base[c * plane + (size_t)u * P.khb + v] = hi;
+          base[(2 + c) * plane + (size_t)u * P.khb + v] = lo;
         }
       }
   }

@@ -125,7 +125,8 @@ struct Plan {
 
   // Operator table image: per offset two planes (re, im) of nu rows of kh
   // floats; columns >= nu are zero. Split precision instead stores, per
-  // offset, planes (re, im) x (hi, lo) of nu rows of khb BF16 values.
+  // offset, planes re.hi, im.hi, re.lo, im.lo (the hi half first) of nu rows
+  // of khb 16-bit values.
   std::vector<float> table;
   std::vector<uint16_t> table_bf16;  // 16-bit image (BF16 or FP16 bits)
   // FP16 forms: operator o is stored divided by off_scale[o] (a power of
