@@ -430,7 +430,7 @@ def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0):
         ff.set_basis(nb_ptr, S_dev)
     nb_total = ff.nb_total
     # the persistent stage-2 grid as the library's autotuner sizes it
-    ff.tune(nrhs=nrhs, reps=3)
+    tune = tune_with_report(ff, nrhs, 3)
     n_vec = 50
     X = torch.from_numpy(W.complex_normal((n_vec, nrhs, nb_total), seed=1000)).to(dev)
     Y = torch.empty((nrhs, nb_total), dtype=torch.complex64, device=dev)
@@ -468,10 +468,48 @@ def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0):
     torch.cuda.synchronize()
     out = {"info": ff.info, "plan_ms": plan_ms, "dt": dt, "value": steps * nrhs / dt,
            "avg_us": stage_ms / len(call_ms) * 1e3, "call_ms": call_ms, "latency": lat,
-           "Y": Ys, "X": X.cpu().numpy(), "nb_ptr": nb_ptr, "S": S, "nb_total": nb_total}
+           "Y": Ys, "X": X.cpu().numpy(), "nb_ptr": nb_ptr, "S": S, "nb_total": nb_total,
+           "tune": tune}
     ff.close()
     del S_dev
     return out
+
+
+KERNEL_NAMES = {0: "chunks", 1: "chunks+rhs-walk", 2: "rounds", 3: "rounds-double-buffer"}
+
+
+def tune_with_report(ff, nrhs, reps):
+    """Run the library's stage-2 autotuner and return what it timed: the
+    chosen kernel and grid and every candidate's time per launch (read back
+    from a transient tuner cache file unless UBF_TUNE_CACHE is set)."""
+    import tempfile
+
+    own = not os.environ.get("UBF_TUNE_CACHE")
+    path = None
+    if own:
+        fd, path = tempfile.mkstemp(prefix="ubf_tune_", suffix=".txt")
+        os.close(fd)
+        os.environ["UBF_TUNE_CACHE"] = path
+    try:
+        groups = ff.tune(nrhs=nrhs, reps=reps)
+        out = {"kernel": KERNEL_NAMES.get(ff.info["translate_kernel"]), "groups": groups}
+        cache = os.environ["UBF_TUNE_CACHE"]
+        try:
+            lines = [l for l in open(cache).read().splitlines() if "\t" in l]
+        except OSError:
+            lines = []
+        if lines:
+            fields = lines[-1].split("\t")[1].split()
+            cands = {}
+            for c in fields[3:]:
+                k, g, us = c.split(":")
+                cands[f"{KERNEL_NAMES.get(int(k), k)}/{g}"] = round(float(us), 2)
+            out["candidates_us"] = cands
+        return out
+    finally:
+        if own:
+            del os.environ["UBF_TUNE_CACHE"]
+            os.remove(path)
 
 
 def latency_loops(U, torch, plan, X, Y, nrhs, stream, n_calls):
@@ -528,7 +566,8 @@ def batch_form(U, W, torch, w, precision, warmup, steps):
     ff = U.FarField(None, w.a, w.k, w.n_d, w.far_mode, max_nrhs=nrhs,
                     precision=precision, scatterers=parts)
     plan_ms = (time.perf_counter() - t0) * 1e3
-    groups = ff.tune(nrhs=nrhs, reps=2)
+    tune = tune_with_report(ff, nrhs, 2)
+    groups = tune["groups"]
     x = torch.from_numpy(w.coefficients()).to("cuda:0")
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream().cuda_stream
@@ -553,7 +592,7 @@ def batch_form(U, W, torch, w, precision, warmup, steps):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     call_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    out = {"info": ff.info, "plan_ms": plan_ms, "dt": dt, "groups": groups,
+    out = {"info": ff.info, "plan_ms": plan_ms, "dt": dt, "groups": groups, "tune": tune,
            "value": steps * nrhs * len(parts) / dt, "avg_us": stage_ms / n_prof * 1e3,
            "call_ms": call_ms, "y": y.cpu().numpy(), "x": x.cpu().numpy()}
     ff.close()
@@ -645,6 +684,7 @@ def bench_batch(args, U, W, torch):
                    "far_mode": w.far_mode, "basis": "identity", "nrhs": nrhs,
                    "precision": chosen, "launch": "one HIP graph (3 kernels) per step",
                    "translate_groups": res["groups"]},
+        "tune": res["tune"],
         "p50_ms": float(np.percentile(res["call_ms"], 50)),
         "p99_ms": float(np.percentile(res["call_ms"], 99)),
         "plan_ms": res["plan_ms"], "stages": stages,
@@ -875,6 +915,7 @@ def main():
                              if S is not None else "identity"),
                    "nrhs": nrhs, "precision": chosen,
                    "translate_groups": info["translate_groups"]},
+        "tune": res["tune"],
         **latency_fields(res["latency"]),
         "plan_ms": res["plan_ms"],
         "stages": stages,

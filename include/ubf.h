@@ -118,9 +118,33 @@ typedef struct ubf_info {
   int32_t n_scatterers;     /* independent scatterers in the plan (>= 1) */
   int32_t translate_groups; /* persistent stage-2 workgroups per RHS */
   int64_t n_items;          /* work items of the kernels that stage box vectors
-                               in LDS (N_u = 192, networks): up to 32 pairs of
-                               one offset each, per RHS */
+                               in LDS (N_u = 192, networks) and of the round
+                               kernels: up to 32 pairs of one offset each,
+                               per RHS */
+  int32_t translate_kernel; /* stage-2 kernel of the 16-bit forms: a value of
+                               enum ubf_translate_kernel, 0 for the FP32 form */
+  int32_t reserved;
 } ubf_info;
+
+/* Stage-2 kernels of the 16-bit forms (ubf_plan_schedule, ubf_plan_tune).
+ * All compute each column with the same products in the same order, so
+ * they agree bit for bit; they differ in how the work is scheduled. */
+enum ubf_translate_kernel {
+  UBF_TRANSLATE_CHUNKS = 0,       /* persistent workgroups over chunks of up to
+                                     128 pairs of one offset, one right-hand
+                                     side per grid row (the FP32 form's only
+                                     schedule) */
+  UBF_TRANSLATE_CHUNKS_WALK = 1,  /* the same, each workgroup taking every
+                                     right-hand side of a chunk in turn (one
+                                     operator staging for all of them) */
+  UBF_TRANSLATE_ROUNDS = 2,       /* rounds of four 32-pair items per
+                                     workgroup, two workgroups per compute unit,
+                                     partial rows stored while the next rows
+                                     compute */
+  UBF_TRANSLATE_ROUNDS_DOUBLE = 3 /* the same at one workgroup per compute unit
+                                     with two operator buffers, the next
+                                     segment's operator copied ahead */
+};
 
 typedef struct ubf_plan ubf_plan;
 
@@ -259,18 +283,38 @@ int ubf_plan_capture(ubf_plan* plan, const void* d_x, void* d_y, int32_t nrhs);
  * UBF_ESTATE (nothing captured), UBF_EDEVICE. */
 int ubf_plan_replay(ubf_plan* plan, void* hip_stream);
 
-/* Autotune the persistent stage-2 grid of a bound plan: time `reps`
- * translation launches for nrhs right-hand sides at each candidate
- * workgroup count (256, 512, 1024, 2048, 4096, capped by the number of
- * work chunks), keep the fastest, and write the chosen count to
- * *groups_out (may be NULL). Runs and waits on hip_stream; overwrites the
+/* Autotune stage 2 of a bound plan, the counterpart of the paper's
+ * scheduling of translations by translation vector (Sec. 4): time `reps`
+ * translation launches for nrhs right-hand sides under each candidate
+ * schedule and keep the fastest. Candidates: the persistent chunk kernel at
+ * 256, 512, 1024, 2048 and 4096 workgroups (capped by the number of
+ * chunks); for the 16-bit forms also the walk over right-hand sides at the
+ * same grids (nrhs > 1), the rounds kernel at 512, 1024 and 2048 workgroups
+ * and the double-buffered rounds kernel at 256. The chosen workgroup count
+ * goes to *groups_out (may be NULL), the kernel to ubf_info's
+ * translate_kernel. If the environment variable UBF_TUNE_CACHE names a
+ * file, a schedule recorded there for the same plan statistics (form, N_u,
+ * nrhs, boxes, scatterers, pairs, offsets, chunks, items) is applied
+ * without timing, and a new choice is appended to it with every
+ * candidate's time. Runs and waits on hip_stream; overwrites the
  * workspace's internal vectors (never x or y). Results of later products
- * do not depend on the choice. Plans whose stage 2 has no persistent grid
- * (networks set, or 192 coefficients per box in FP32) are left as they
- * are. Errors: UBF_EINVAL (null plan, nrhs out of 1..max_nrhs, reps out of
- * 1..1000), UBF_ESTATE (unbound), UBF_EDEVICE. */
+ * do not depend on the choice (bit for bit). Plans whose stage 2 has no
+ * persistent grid (networks set, or 192 coefficients per box in FP32) are
+ * left as they are. Any captured graph is discarded. Errors: UBF_EINVAL
+ * (null plan, nrhs out of 1..max_nrhs, reps out of 1..1000), UBF_ESTATE
+ * (unbound), UBF_EDEVICE. */
 int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
                   int32_t* groups_out);
+
+/* Set stage 2 of a bound plan to a given schedule (what ubf_plan_tune
+ * would choose): kernel is an enum ubf_translate_kernel value (only 0 for
+ * the FP32 form), groups the persistent workgroup count (1..4096, rounded
+ * up to a multiple of 8 and capped by the work units). Uploads the work
+ * partition on hip_stream and waits. Results do not depend on the choice.
+ * Any captured graph is discarded. Errors: UBF_EINVAL (null plan, unknown
+ * kernel, a 16-bit kernel on an FP32 plan, groups out of range),
+ * UBF_ESTATE (unbound), UBF_EDEVICE. */
+int ubf_plan_schedule(ubf_plan* plan, int32_t kernel, int32_t groups, void* hip_stream);
 
 /* Stage 1 alone: d_P[nrhs][n_boxes][N_u] = S_i x_i (complex64). */
 int ubf_aggregate(ubf_plan* plan, const void* d_x, void* d_P, int32_t nrhs,

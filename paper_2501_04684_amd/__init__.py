@@ -21,7 +21,7 @@ __all__ = [
     "UbfError", "FAR_ILIST", "FAR_FULL", "FP32", "SPLIT_BF16", "SPLIT_FP16", "FP16", "lib",
     "library_path",
     "declared_symbols", "plan_create", "plan_create_batch", "workspace_bytes",
-    "plan_bind", "plan_capture", "plan_replay", "plan_tune",
+    "plan_bind", "plan_capture", "plan_replay", "plan_tune", "plan_schedule",
     "plan_set_basis", "network_bytes", "plan_set_networks", "far_mvm", "far_mvm_noalloc",
     "aggregate", "translate", "disaggregate",
     "plan_info", "plan_offsets", "plan_far_pairs", "plan_operator",
@@ -40,6 +40,8 @@ library_path = os.environ.get("UBF_LIBRARY") or os.path.join(HERE, "libubf.so")
 
 FAR_ILIST, FAR_FULL = 0, 1
 FP32, SPLIT_BF16, SPLIT_FP16, FP16 = 0, 1, 2, 3
+# stage-2 kernels of the 16-bit forms (enum ubf_translate_kernel)
+TRANSLATE_CHUNKS, TRANSLATE_CHUNKS_WALK, TRANSLATE_ROUNDS, TRANSLATE_ROUNDS_DOUBLE = 0, 1, 2, 3
 _PRECISIONS = {"fp32": FP32, "split-bf16": SPLIT_BF16, "split-fp16": SPLIT_FP16,
                "fp16": FP16, FP32: FP32, SPLIT_BF16: SPLIT_BF16, SPLIT_FP16: SPLIT_FP16,
                FP16: FP16}
@@ -69,7 +71,8 @@ class _Info(ctypes.Structure):
                 ("n_chunks", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("translate_flops", ctypes.c_double), ("mfma", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_scatterers", ctypes.c_int32),
-                ("translate_groups", ctypes.c_int32), ("n_items", ctypes.c_int64)]
+                ("translate_groups", ctypes.c_int32), ("n_items", ctypes.c_int64),
+                ("translate_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _GmresStatus(ctypes.Structure):
@@ -95,6 +98,7 @@ _SIGS = {
     "ubf_plan_capture": (ctypes.c_int, [_VP, _VP, _VP, _I32]),
     "ubf_plan_replay": (ctypes.c_int, [_VP, _VP]),
     "ubf_plan_tune": (ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
+    "ubf_plan_schedule": (ctypes.c_int, [_VP, _I32, _I32, _VP]),
     "ubf_aggregate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
     "ubf_translate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
     "ubf_disaggregate": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP]),
@@ -279,11 +283,18 @@ def plan_replay(plan, stream=None):
 
 
 def plan_tune(plan, nrhs: int = 1, reps: int = 5, stream=None) -> int:
-    """Autotune the persistent stage-2 grid; returns the chosen group count."""
+    """Autotune the stage-2 schedule; returns the chosen group count (the
+    kernel is plan_info()["translate_kernel"])."""
     g = ctypes.c_int32(0)
     _check(lib().ubf_plan_tune(plan, int(nrhs), int(reps), _stream(stream),
                                ctypes.byref(g)), "ubf_plan_tune")
     return g.value
+
+
+def plan_schedule(plan, kernel: int, groups: int, stream=None):
+    """Set the stage-2 kernel (enum ubf_translate_kernel) and workgroups."""
+    _check(lib().ubf_plan_schedule(plan, int(kernel), int(groups), _stream(stream)),
+           "ubf_plan_schedule")
 
 
 def aggregate(plan, x, P, nrhs=None, stream=None):
@@ -500,6 +511,10 @@ class FarField:
         g = plan_tune(self.plan, self.max_nrhs if nrhs is None else nrhs, reps)
         self.info = plan_info(self.plan)
         return g
+
+    def schedule(self, kernel, groups):
+        plan_schedule(self.plan, kernel, groups)
+        self.info = plan_info(self.plan)
 
     def capture(self, x, y):
         """Record y = T G S x for these two tensors; run it with replay()."""

@@ -1,7 +1,10 @@
 // C ABI of the far-zone product (declared in include/ubf.h).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -134,6 +137,110 @@ int create(const ubf_problem* problem, const int64_t* scat_ptr, int64_t n_scat,
 }
 
 
+// ---------------------------------------------------------------- tuner
+
+// Persistent grid of the plan's current stage-2 kernel.
+int current_groups(const ubf::Plan& p) {
+  return (p.split() && (p.split_kernel == ubf::kSplitRounds ||
+                        p.split_kernel == ubf::kSplitRoundsDouble))
+             ? p.n_round_groups()
+             : p.n_groups();
+}
+
+// Select a stage-2 kernel and grid, and upload the work partition it reads.
+int apply_schedule(ubf::Plan& p, int kernel, int64_t groups, hipStream_t s) {
+  p.split_kernel = p.split() ? kernel : ubf::kSplitChunks;
+  hipError_t e;
+  if (p.split_kernel == ubf::kSplitRounds || p.split_kernel == ubf::kSplitRoundsDouble) {
+    ubf::build_rounds(p, groups);
+    e = hipMemcpyAsync(p.d_rounds, p.rounds.data(), p.rounds.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p.d_wg_round_ptr, p.wg_round_ptr.data(),
+                         p.wg_round_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  } else {
+    ubf::partition_groups(p, groups);
+    e = hipMemcpyAsync(p.d_wg_ptr, p.wg_ptr.data(), p.wg_ptr.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return (int)e;
+}
+
+struct Candidate {
+  int kernel;
+  int64_t groups;
+};
+
+// Stage-2 schedules the tuner times: persistent chunk grids of 256..4096
+// workgroups; for the 16-bit forms also the walk over right-hand sides
+// (several vectors), the rounds at two workgroups per compute unit
+// (512..2048) and the double-buffered rounds at one (256). Grids that the
+// work caps to the same size are timed once.
+std::vector<Candidate> tune_candidates(const ubf::Plan& p, int nrhs) {
+  std::vector<Candidate> c;
+  const int64_t grids[] = {256, 512, 1024, 2048, 4096};
+  auto capped = [](int64_t g, int64_t units) {
+    g = std::min<int64_t>(g, std::max<int64_t>(units, 1));
+    return std::min<int64_t>((g + 7) / 8 * 8, ubf::kMaxTranslateGroups);
+  };
+  auto add = [&](int kernel, int64_t g, int64_t units) {
+    const int64_t eff = capped(g, units);
+    for (const Candidate& x : c)
+      if (x.kernel == kernel && x.groups == eff) return;
+    c.push_back({kernel, eff});
+  };
+  for (int64_t g : grids) add(ubf::kSplitChunks, g, p.n_chunks());
+  if (p.split()) {
+    if (nrhs > 1)
+      for (int64_t g : grids) add(ubf::kSplitChunksWalk, g, p.n_chunks());
+    for (int64_t g : {512, 1024, 2048}) add(ubf::kSplitRounds, g, p.n_items());
+    add(ubf::kSplitRoundsDouble, 256, p.n_items());
+  }
+  return c;
+}
+
+// The plan statistics a schedule is chosen for: the stage-2 form, box size,
+// vectors per call and the sizes of the far set and its partition.
+std::string tune_key(const ubf::Plan& p, int nrhs) {
+  return "v1 precision=" + std::to_string(p.precision) + " nu=" + std::to_string(p.nu) +
+         " nrhs=" + std::to_string(nrhs) + " boxes=" + std::to_string(p.n_box) +
+         " scatterers=" + std::to_string(p.n_scat()) + " pairs=" + std::to_string(p.n_pairs()) +
+         " offsets=" + std::to_string(p.n_off()) + " chunks=" + std::to_string(p.n_chunks()) +
+         " items=" + std::to_string(p.n_items());
+}
+
+// Cache file (UBF_TUNE_CACHE): one line per key, "<key>\t<kernel> <groups>
+// <ms> <timings>". The last line of a key wins.
+bool cache_lookup(const char* path, const std::string& key, int* kernel, int* groups) {
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char line[4096];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* tab = std::strchr(line, '\t');
+    if (!tab || (size_t)(tab - line) != key.size() || key.compare(0, key.size(), line, key.size()))
+      continue;
+    int k = -1, g = 0;
+    if (std::sscanf(tab + 1, "%d %d", &k, &g) == 2 && k >= 0 && k <= ubf::kSplitRoundsDouble &&
+        g >= 1 && g <= ubf::kMaxTranslateGroups) {
+      *kernel = k;
+      *groups = g;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, int kernel, int groups, float ms,
+                 const std::string& report) {
+  std::FILE* f = std::fopen(path, "a");
+  if (!f) return;  // a cache that cannot be written only costs the next tuning
+  std::fprintf(f, "%s\t%d %d %.6f%s\n", key.c_str(), kernel, groups, (double)ms, report.c_str());
+  std::fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -185,6 +292,8 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
       {L.chunks, p.chunks.data(), p.chunks.size() * sizeof(int32_t)},
       {L.items, p.items.data(), p.items.size() * sizeof(int32_t)},
       {L.wg_ptr, p.wg_ptr.data(), p.wg_ptr.size() * sizeof(int32_t)},
+      {L.rounds, p.rounds.data(), p.rounds.size() * sizeof(int32_t)},
+      {L.wg_round_ptr, p.wg_round_ptr.data(), p.wg_round_ptr.size() * sizeof(int32_t)},
       {L.pair_src, p.pair_src.data(), p.pair_src.size() * sizeof(int32_t)},
       {L.pair_dst, p.pair_dst.data(), p.pair_dst.size() * sizeof(int32_t)},
       {L.test_ptr, p.test_ptr.data(), p.test_ptr.size() * sizeof(int32_t)},
@@ -205,6 +314,8 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
   p.d_chunks = (int32_t*)(ws + L.chunks);
   p.d_items = (int32_t*)(ws + L.items);
   p.d_wg_ptr = (int32_t*)(ws + L.wg_ptr);
+  p.d_rounds = (int32_t*)(ws + L.rounds);
+  p.d_wg_round_ptr = (int32_t*)(ws + L.wg_round_ptr);
   p.d_pair_src = (int32_t*)(ws + L.pair_src);
   p.d_test_ptr = (int32_t*)(ws + L.test_ptr);
   p.d_pair_dst = (int32_t*)(ws + L.pair_dst);
@@ -303,6 +414,22 @@ int ubf_plan_replay(ubf_plan* plan, void* hip_stream) {
   return ok();
 }
 
+int ubf_plan_schedule(ubf_plan* plan, int32_t kernel, int32_t groups, void* hip_stream) {
+  if (!plan) return fail(UBF_EINVAL, "plan is NULL");
+  ubf::Plan& p = plan->p;
+  if (!p.ws) return fail(UBF_ESTATE, "plan is not bound to a workspace");
+  if (kernel < 0 || kernel > ubf::kSplitRoundsDouble)
+    return fail(UBF_EINVAL, "unknown stage-2 kernel");
+  if (kernel != ubf::kSplitChunks && !p.split())
+    return fail(UBF_EINVAL, "only the 16-bit forms have stage-2 kernels other than 0");
+  if (groups < 1 || groups > ubf::kMaxTranslateGroups)
+    return fail(UBF_EINVAL, "groups must be in 1.." + std::to_string(ubf::kMaxTranslateGroups));
+  plan->drop_graph();
+  const int e = apply_schedule(p, kernel, groups, (hipStream_t)hip_stream);
+  if (e) return hip_fail(e, "upload (schedule)");
+  return ok();
+}
+
 int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
                   int32_t* groups_out) {
   if (!plan) return fail(UBF_EINVAL, "plan is NULL");
@@ -312,12 +439,21 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
     return fail(UBF_EINVAL, "nrhs must be in 1..max_nrhs of the binding");
   if (reps < 1 || reps > 1000) return fail(UBF_EINVAL, "reps must be in 1..1000");
   if (p.hidden > 0 || ubf::staged_translate_supported(p)) {
-    // stage 2 runs one workgroup per 32 pairs here: no persistent grid to size
+    // stage 2 runs one workgroup per 32 pairs here: nothing to choose
     if (groups_out) *groups_out = (int32_t)p.n_groups();
     return ok();
   }
   plan->drop_graph();
   hipStream_t s = (hipStream_t)hip_stream;
+  const std::string key = tune_key(p, nrhs);
+  const char* cache = std::getenv("UBF_TUNE_CACHE");
+  int kernel = -1, groups = 0;
+  if (cache && *cache && cache_lookup(cache, key, &kernel, &groups)) {
+    const int e = apply_schedule(p, kernel, groups, s);
+    if (e) return hip_fail(e, "upload (tune cache)");
+    if (groups_out) *groups_out = current_groups(p);
+    return ok();
+  }
   const ubf::Layout L = ubf::workspace_layout(p, p.max_nrhs);
   // Column values do not change the timing; start them from zero.
   hipError_t e = hipMemsetAsync(p.d_P, 0, L.part - L.P, s);
@@ -328,23 +464,16 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
     (void)hipEventDestroy(t0);
     return hip_fail(e, "hipEventCreate");
   }
-  auto upload = [&]() -> hipError_t {
-    hipError_t r = hipMemcpyAsync(p.d_wg_ptr, p.wg_ptr.data(),
-                                  p.wg_ptr.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, s);
-    return r != hipSuccess ? r : hipStreamSynchronize(s);
-  };
-  const int64_t before = p.n_groups();
-  int64_t best = before;
+  const int before_kernel = p.split_kernel;
+  const int before_groups = current_groups(p);
+  int best_kernel = before_kernel, best_groups = before_groups;
   float best_ms = 0.f;
   int status = UBF_OK;
-  std::string why;
-  const int64_t cands[] = {256, 512, 1024, 2048, 4096};
-  for (int64_t c : cands) {
-    ubf::partition_groups(p, c);
-    if (p.n_groups() != c && c != cands[0]) continue;  // capped by the chunk count
-    if ((e = upload()) != hipSuccess) { status = hip_fail(e, "upload (tune)"); break; }
-    int le = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, s);  // warm-up
+  std::string why, report;
+  for (const Candidate& c : tune_candidates(p, nrhs)) {
+    int le = apply_schedule(p, c.kernel, c.groups, s);
+    if (le) { status = hip_fail(le, "upload (tune)"); break; }
+    le = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, s);  // warm-up
     if (!le && hipEventRecord(t0, s) != hipSuccess) le = (int)hipGetLastError();
     for (int r = 0; r < reps && !le; ++r) le = ubf::launch_translate(p, p.d_P, p.d_part, nrhs, s);
     if (!le && hipEventRecord(t1, s) != hipSuccess) le = (int)hipGetLastError();
@@ -352,22 +481,26 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
     float ms = 0.f;
     if (!le) le = (int)hipEventElapsedTime(&ms, t0, t1);
     if (le) { status = hip_fail(le, "translate (tune)"); break; }
+    ms /= (float)reps;
+    report += " " + std::to_string(c.kernel) + ":" + std::to_string(current_groups(p)) + ":" +
+              std::to_string(ms * 1e3f);
     if (best_ms == 0.f || ms < best_ms) {
       best_ms = ms;
-      best = p.n_groups();
+      best_kernel = c.kernel;
+      best_groups = current_groups(p);
     }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (status != UBF_OK) {
     why = ubf::last_error_text();
-    ubf::partition_groups(p, before);
-    (void)upload();
+    (void)apply_schedule(p, before_kernel, before_groups, s);
     return fail(status, why);
   }
-  ubf::partition_groups(p, best);
-  if ((e = upload()) != hipSuccess) return hip_fail(e, "upload (tune)");
-  if (groups_out) *groups_out = (int32_t)p.n_groups();
+  if ((e = (hipError_t)apply_schedule(p, best_kernel, best_groups, s)) != hipSuccess)
+    return hip_fail(e, "upload (tune)");
+  if (cache && *cache) cache_store(cache, key, best_kernel, best_groups, best_ms, report);
+  if (groups_out) *groups_out = current_groups(p);
   return ok();
 }
 
@@ -521,8 +654,9 @@ int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
   out->mfma = (ubf::translate_uses_mfma(p) || ubf::staged_translate_supported(p)) ? 1 : 0;
   out->precision = p.precision;
   out->n_scatterers = p.n_scat();
-  out->translate_groups = p.n_groups();
   out->n_items = p.n_items();
+  out->translate_kernel = p.split_kernel;
+  out->translate_groups = current_groups(p);
   return ok();
 }
 

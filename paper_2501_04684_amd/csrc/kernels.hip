@@ -598,13 +598,13 @@ __device__ inline void copy_to_lds(const uintx4* __restrict__ src, uintx4* dst) 
 // each block is written as 4-row pieces per column, read back as 8 columns
 // x 128 contiguous bytes per store instruction, the destination rows taken
 // once per chunk from their owner lanes.
-template <int NU, bool F16, int NPROD>
+template <int NU, bool F16, int NPROD, bool WALK>
 __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const unsigned short* __restrict__ table, const int32_t* __restrict__ chunks,
     const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
     const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
     float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row,
-    const float* __restrict__ off_scale, const float* __restrict__ box_scale) {
+    const float* __restrict__ off_scale, const float* __restrict__ box_scale, int nrhs) {
   typedef typename Mfma16<F16>::vec vec16;
   constexpr int KH = (NU + 3) & ~3;      // FP32 half-length (partial rows)
   constexpr int KHB = (NU + 7) & ~7;     // 16-bit half-length
@@ -624,7 +624,11 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
 
   const int group = xcd_chunk(blockIdx.x, gridDim.x);
   const int cbeg = wg_ptr[group], cend = wg_ptr[group + 1];
-  const int rhs = blockIdx.y;
+  // WALK: the workgroup walks work units v = chunk * nrhs + rhs over its
+  // chunks (every right-hand side of a chunk in turn, one staging of the
+  // operator for all of them); otherwise one right-hand side per grid row
+  const int nv = WALK ? nrhs : 1;
+  const int vbeg = cbeg * nv, vend = cend * nv;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
 
@@ -646,13 +650,17 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   const int col0 = wave * 32;
   const int64_t last = n_pairs - 1;
 
-  // Unconditional memory operations, pair indices two chunks ahead, B
-  // values one chunk ahead (refilled in pass 2).
+  // Unconditional memory operations, pair indices two units ahead, B
+  // values one unit ahead (refilled in pass 2).
+  auto unit_rhs = [&](int v) { return WALK ? v % nv : (int)blockIdx.y; };
   int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
-  const bool has1 = cbeg + 1 < cend;
-  int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
-  int b1 = has1 ? chunks[4 * (cbeg + 1) + 1] : 0;
-  int n1 = has1 ? chunks[4 * (cbeg + 1) + 2] : 0;
+  int rhs0 = unit_rhs(vbeg);
+  const bool has1 = vbeg + 1 < vend;
+  const int c1 = (vbeg + 1) / nv;
+  int rhs1 = has1 ? unit_rhs(vbeg + 1) : rhs0;
+  int o1 = has1 ? chunks[4 * c1] : o0;
+  int b1 = has1 ? chunks[4 * c1 + 1] : 0;
+  int n1 = has1 ? chunks[4 * c1 + 2] : 0;
   int64_t i0 = min((int64_t)b0 + col0 + r, last), i1 = min((int64_t)b1 + col0 + r, last);
   int src0 = pair_src[i0], dst0 = pair_dst[i0];
   int src1 = pair_src[i1], dst1 = pair_dst[i1];
@@ -660,7 +668,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   // k-step g of a box vector is 64 bytes: hi of both halves, then lo of both
   vec16 bh[NGB], bl[NPROD == 3 ? NGB : 1];
   {
-    const vec16* pv = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src0) * VSTR);
+    const vec16* pv = reinterpret_cast<const vec16*>(P + ((int64_t)rhs0 * n_box + src0) * VSTR);
 #pragma unroll
     for (int g = 0; g < NGB; ++g) {
       bh[g] = pv[4 * g + h];
@@ -668,10 +676,10 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     }
   }
   // FP16: the scale of the current chunk's column (this lane's source box)
-  float bsc0 = F16 ? box_scale[(int64_t)rhs * n_box + src0] : 1.f, bsc1 = 1.f;
+  float bsc0 = F16 ? box_scale[(int64_t)rhs0 * n_box + src0] : 1.f, bsc1 = 1.f;
 
   int staged = -1;
-  for (int ch = cbeg; ch < cend; ++ch) {
+  for (int v = vbeg; v < vend; ++v) {
     const bool restage = o0 != staged;  // uniform across the workgroup
     if (restage) {
       // both halves through registers: the hi half's units, then the lo half's
@@ -691,10 +699,12 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
       __syncthreads();
       staged = o0;
     }
-    const bool has2 = ch + 2 < cend;
-    const int o2 = has2 ? chunks[4 * (ch + 2)] : o1;
-    const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
-    const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
+    const bool has2 = v + 2 < vend;
+    const int c2 = (v + 2) / nv;
+    const int rhs2 = has2 ? unit_rhs(v + 2) : rhs1;
+    const int o2 = has2 ? chunks[4 * c2] : o1;
+    const int b2 = has2 ? chunks[4 * c2 + 1] : 0;
+    const int n2 = has2 ? chunks[4 * c2 + 2] : 0;
     const int64_t i2 = min((int64_t)b2 + col0 + r, last);
     const bool active = col0 < n0;  // wave-uniform
 
@@ -722,8 +732,8 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     }
     // the next chunk's column (its index arrived long ago): its box vector
     // is fetched in pass 2, its FP16 scale here
-    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src1) * VSTR);
-    if (F16) bsc1 = box_scale[(int64_t)rhs * n_box + src1];
+    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs1 * n_box + src1) * VSTR);
+    if (F16) bsc1 = box_scale[(int64_t)rhs1 * n_box + src1];
     if (active) {
       // pass 2: Gl Ph, refilling the registers with the next chunk's columns
 #pragma unroll
@@ -755,7 +765,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     if (active) {
       const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
       float* tile = reinterpret_cast<float*>(tiles4[wave]);
-      float* part_rhs = part + (int64_t)rhs * n_pairs * PSTR;
+      float* part_rhs = part + (int64_t)rhs0 * n_pairs * PSTR;
       const int seg = lane & 7;
       // destination row of the columns this lane stores (c = lane/8 + 8 it)
       int64_t rowoff[4];
@@ -785,9 +795,254 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
             *reinterpret_cast<floatx4*>(part_rhs + rowoff[it] + m) = v[it];
       }
     }
-    o0 = o1; n0 = n1; dst0 = dst1;
-    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;
+    o0 = o1; n0 = n1; dst0 = dst1; rhs0 = rhs1;
+    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2; rhs1 = rhs2;
     bsc0 = bsc1;
+  }
+}
+
+// The split-precision translation in rounds of four items per workgroup of
+// four wavefronts, so that a wavefront's memory traffic overlaps its own
+// matrix-core work. Two workgroups per compute unit with one operator
+// buffer each (DOUBLE = false), or one per compute unit with two buffers
+// (DOUBLE = true: the next segment's operator is copied during this one):
+// * each workgroup walks its rounds (p.rounds); in a round, wavefront w
+//   takes one item (up to 32 pairs of one offset, one column each) of the
+//   current segment (a run of one offset);
+// * a segment's operator is copied straight into LDS (global -> LDS, no
+//   registers); with two buffers, the next segment's copy is issued when a
+//   segment starts and arrives while that segment runs;
+// * pass 1 accumulates Gh Ph (+ Gh Pl) over all k-steps into every 32-row
+//   block; pass 2 adds Gl Ph block pair by block pair, so each pair is
+//   complete, and its partial rows are stored (through the wavefront's
+//   transposing LDS tile), while the next pair computes;
+// * the next item's columns are fetched during pass 2.
+// Columns past an item's count repeat its last pair (same values stored to
+// the same row again), so no store is masked. Per column the arithmetic is
+// the same products as translate_split_kernel, accumulated in another order.
+template <int NU, bool F16, int NPROD, bool DOUBLE>
+__global__ __launch_bounds__(kBlock, DOUBLE ? 1 : 2) void translate_rounds_kernel(
+    const unsigned short* __restrict__ table, const int32_t* __restrict__ rounds,
+    const int32_t* __restrict__ wg_round_ptr, const int32_t* __restrict__ pair_src,
+    const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
+    float* __restrict__ part, int64_t n_box, int64_t n_pairs,
+    const float* __restrict__ off_scale, const float* __restrict__ box_scale) {
+  typedef typename Mfma16<F16>::vec vec16;
+  constexpr int KH = (NU + 3) & ~3;
+  constexpr int KHB = (NU + 7) & ~7;
+  constexpr int PLANE = NU * KHB;
+  constexpr int M = 2 * NU;
+  constexpr int RB = (M + 31) / 32;
+  constexpr int NGB = KHB / 8;
+  constexpr int PSTR = 2 * KH;
+  constexpr int VSTR = 2 * KHB;
+  constexpr int H16 = 2 * PLANE * 2 / 16;
+  constexpr int HPAD = (H16 + kBlock - 1) / kBlock * kBlock;
+  constexpr int OPB = (NPROD == 3 ? 2 : 1) * HPAD;  // 16-byte units per operator buffer
+  constexpr int LO = HPAD * 8;                      // lo half, in 16-bit values
+  // rows of the last 32-row block that belong to the partial row
+  constexpr int LR = PSTR - 32 * (RB - 1);
+  static_assert(LR % 8 == 0 && LR <= 32, "rows of the last block");
+  __shared__ uintx4 opbuf0[OPB];
+  __shared__ uintx4 opbuf1[DOUBLE ? OPB : 1];
+  __shared__ floatx4 tiles4[4][32 * kTilePitch / 4];
+
+  const int group = xcd_chunk(blockIdx.x, gridDim.x);
+  const int kbeg = wg_round_ptr[group], kend = wg_round_ptr[group + 1];
+  const int rhs = blockIdx.y;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5, seg = lane & 7;
+
+  int abase[RB];
+  unsigned asgn[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int row = rb * 32 + r;
+    const bool er = row < NU;
+    const int rr = er ? row : (row < M ? row - NU : 0);
+    const int c = er ? (h == 1 ? 1 : 0) : (row < M && h == 0 ? 1 : 0);
+    abase[rb] = c * PLANE + rr * KHB;
+    asgn[rb] = (er && h == 1) ? 0x80008000u : 0u;
+  }
+  if (kbeg >= kend) return;
+
+  const int4* rd = reinterpret_cast<const int4*>(rounds);
+  const int64_t last = n_pairs - 1;
+  float* tile = reinterpret_cast<float*>(tiles4[wave]);
+  float* part_rhs = part + (int64_t)rhs * n_pairs * PSTR;
+  auto copy_operator = [&](int o, uintx4* dst) {
+    const uintx4* g4 = reinterpret_cast<const uintx4*>(table + (size_t)o * 4 * PLANE);
+    copy_to_lds<H16>(g4, dst);
+    if (NPROD == 3) copy_to_lds<H16>(g4 + H16, dst + HPAD);
+  };
+  auto column = [&](const int4& d) {
+    return min((int64_t)d.y + min(r, max(d.z - 1, 0)), last);
+  };
+
+  // this wavefront's items of rounds k, k+1 (descriptors) and their columns
+  int4 d0 = rd[(int64_t)kbeg * 4 + wave];
+  int4 d1 = kbeg + 1 < kend ? rd[(int64_t)(kbeg + 1) * 4 + wave] : int4{0, 0, 0, 0};
+  const int64_t i0 = column(d0), i1 = column(d1);
+  int src0 = pair_src[i0], dst0 = pair_dst[i0];
+  int src1 = pair_src[i1], dst1 = pair_dst[i1];
+  vec16 bh[NGB], bl[NPROD == 3 ? NGB : 1];
+  {
+    const vec16* pv = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src0) * VSTR);
+#pragma unroll
+    for (int g = 0; g < NGB; ++g) {
+      bh[g] = pv[4 * g + h];
+      if (NPROD == 3) bl[g] = pv[4 * g + 2 + h];
+    }
+  }
+  float bsc0 = F16 ? box_scale[(int64_t)rhs * n_box + src0] : 1.f;
+
+  // one round with the current segment's operator in `cur`
+  auto round = [&](const uintx4* cur, int k) {
+    // Indices two rounds ahead and the next item's scale are requested
+    // before this round's stores: a later wait for them then lets the
+    // stores stay in flight (vector memory operations complete in order).
+    const bool has2 = k + 2 < kend;
+    const int4 d2 = has2 ? rd[(int64_t)(k + 2) * 4 + wave] : int4{0, 0, 0, 0};
+    const int64_t i2 = column(d2);
+    const int src2 = pair_src[i2];
+    const int dst2 = pair_dst[i2];
+    const float bsc1 = F16 ? box_scale[(int64_t)rhs * n_box + src1] : 1.f;
+    const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs * n_box + src1) * VSTR);
+
+    if (d0.z > 0) {  // wave-uniform: this wavefront has an item in this round
+      const unsigned short* opb = reinterpret_cast<const unsigned short*>(cur);
+      const float sc = F16 ? off_scale[d0.x] * bsc0 : 1.f;
+      // destination rows of the columns this lane stores: full blocks, lane l
+      // takes column l/8 + 8 it, rows 4 (l%8) .. +3; the last block, column
+      // l/2, rows 4 (l%2) + 8 it .. +3
+      int row_f[4];
+#pragma unroll
+      for (int it = 0; it < 4; ++it) row_f[it] = __shfl(dst0, (lane >> 3) + 8 * it, 64);
+      const int row_l = __shfl(dst0, lane >> 1, 64);
+      floatx16 acc[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+      auto store_block = [&](int rb) {
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+          *reinterpret_cast<floatx4*>(tile + r * kTilePitch + 8 * q4 + 4 * h) =
+              floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                      acc[rb][4 * q4 + 3]} * sc;
+        if (rb < RB - 1) {
+          floatx4 v[4];
+#pragma unroll
+          for (int it = 0; it < 4; ++it)
+            v[it] = *reinterpret_cast<const floatx4*>(
+                tile + ((lane >> 3) + 8 * it) * kTilePitch + 4 * seg);
+#pragma unroll
+          for (int it = 0; it < 4; ++it)
+            *reinterpret_cast<floatx4*>(part_rhs + (int64_t)row_f[it] * PSTR + rb * 32 +
+                                        4 * seg) = v[it];
+        } else {
+          floatx4 v[LR / 8];
+#pragma unroll
+          for (int it = 0; it < LR / 8; ++it)
+            v[it] = *reinterpret_cast<const floatx4*>(tile + (lane >> 1) * kTilePitch +
+                                                      4 * (lane & 1) + 8 * it);
+#pragma unroll
+          for (int it = 0; it < LR / 8; ++it)
+            *reinterpret_cast<floatx4*>(part_rhs + (int64_t)row_l * PSTR + rb * 32 +
+                                        4 * (lane & 1) + 8 * it) = v[it];
+        }
+      };
+
+      // pass 1: Gh Ph (+ Gh Pl) into every block
+#pragma unroll
+      for (int g = 0; g < NGB; ++g) {
+        vec16 a_h[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          uintx4 ah = *reinterpret_cast<const uintx4*>(opb + abase[rb] + 8 * g);
+          ah ^= asgn[rb];
+          a_h[rb] = __builtin_bit_cast(vec16, ah);
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_h[rb], bh[g], acc[rb]);
+        if (NPROD == 3) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_h[rb], bl[g], acc[rb]);
+        }
+      }
+      if (NPROD == 3) {
+        // the lo halves of this column are used up: fetch the next item's
+#pragma unroll
+        for (int g = 0; g < NGB; ++g) bl[g] = pv1[4 * g + 2 + h];
+        // pass 2: Gl Ph, two blocks at a time; a finished pair is stored
+        // while the next pair computes
+#pragma unroll
+        for (int q = 0; q < RB; q += 2) {
+          const bool two = q + 1 < RB;
+#pragma unroll
+          for (int g = 0; g < NGB; ++g) {
+            uintx4 a0 = *reinterpret_cast<const uintx4*>(opb + LO + abase[q] + 8 * g);
+            a0 ^= asgn[q];
+            acc[q] = Mfma16<F16>::run(__builtin_bit_cast(vec16, a0), bh[g], acc[q]);
+            if (two) {
+              uintx4 a1 = *reinterpret_cast<const uintx4*>(opb + LO + abase[q + 1] + 8 * g);
+              a1 ^= asgn[q + 1];
+              acc[q + 1] = Mfma16<F16>::run(__builtin_bit_cast(vec16, a1), bh[g], acc[q + 1]);
+            }
+            if (q + 2 >= RB) bh[g] = pv1[4 * g + h];  // last use of bh[g]
+          }
+          store_block(q);
+          if (two) store_block(q + 1);
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < NGB; ++g) bh[g] = pv1[4 * g + h];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) store_block(rb);
+      }
+    } else {  // no item for this wavefront in this round: fetch the next
+#pragma unroll
+      for (int g = 0; g < NGB; ++g) {
+        bh[g] = pv1[4 * g + h];
+        if (NPROD == 3) bl[g] = pv1[4 * g + 2 + h];
+      }
+    }
+    d0 = d1; d1 = d2;
+    src0 = src1; dst0 = dst1; src1 = src2; dst1 = dst2;
+    bsc0 = bsc1;
+  };
+
+  // segments alternate between the two buffers: even ones read opbuf0 (the
+  // next operator is copied into opbuf1), odd ones the reverse
+  if constexpr (DOUBLE) {
+    // segments alternate between the two buffers: even ones read opbuf0
+    // (the next operator is copied into opbuf1), odd ones the reverse
+    bool odd = true;
+    for (int k = kbeg; k < kend; ++k) {
+      if (d0.w & 1) {  // a segment starts (uniform across the workgroup)
+        if (k == kbeg) copy_operator(d0.x, opbuf0);
+        odd = !odd;
+        // this wavefront's copies of the operator (and everything older)
+        // have landed; after the barrier every wavefront's have, and every
+        // wavefront is done with the other buffer
+        wait_vmcnt<0>();
+        lds_copies_done_barrier();
+        const int next = (d0.w >> 1) - 1;
+        if (next >= 0) copy_operator(next, odd ? opbuf0 : opbuf1);
+      }
+      if (odd) round(opbuf1, k);
+      else round(opbuf0, k);
+    }
+  } else {
+    // one buffer: a segment's operator is copied when it starts
+    for (int k = kbeg; k < kend; ++k) {
+      if (d0.w & 1) {  // a segment starts (uniform across the workgroup)
+        if (k != kbeg) lds_reads_done_barrier();  // every wavefront is done with the operator
+        copy_operator(d0.x, opbuf0);
+        wait_vmcnt<0>();
+        lds_copies_done_barrier();
+      }
+      round(opbuf0, k);
+    }
   }
 }
 
@@ -1225,10 +1480,31 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
   const int64_t trash = (int64_t)p.max_nrhs * p.n_pairs();
   if (p.split()) {
     const unsigned short* tb = reinterpret_cast<const unsigned short*>(p.d_table);
-#define UBF_SPLIT(NU, F16, NPROD)                                                         \
-  UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD>), groups, dim3(kBlock), s, tb,      \
-             p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,         \
-             p.n_pairs(), trash, p.d_off_scale, p.d_box_scale)
+    const int sk = p.split_kernel;
+    const bool walk = sk == kSplitChunksWalk && nrhs > 1;
+    const dim3 cgrid((unsigned)p.n_groups(), walk ? 1 : nrhs);
+    const dim3 rgrid((unsigned)p.n_round_groups(), nrhs);
+#define UBF_SPLIT(NU, F16, NPROD)                                                              \
+  do {                                                                                         \
+    if (sk == kSplitRounds || sk == kSplitRoundsDouble) {                                      \
+      if (sk == kSplitRoundsDouble)                                                            \
+        UBF_LAUNCH(ev, (translate_rounds_kernel<NU, F16, NPROD, true>), rgrid, dim3(kBlock), s,  \
+                   tb, p.d_rounds, p.d_wg_round_ptr, p.d_pair_src, p.d_pair_dst, P, part,      \
+                   p.n_box, p.n_pairs(), p.d_off_scale, p.d_box_scale);                        \
+      else                                                                                     \
+        UBF_LAUNCH(ev, (translate_rounds_kernel<NU, F16, NPROD, false>), rgrid, dim3(kBlock), s, \
+                   tb, p.d_rounds, p.d_wg_round_ptr, p.d_pair_src, p.d_pair_dst, P, part,      \
+                   p.n_box, p.n_pairs(), p.d_off_scale, p.d_box_scale);                        \
+    } else if (walk) {                                                                         \
+      UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD, true>), cgrid, dim3(kBlock), s, tb, \
+                 p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,         \
+                 p.n_pairs(), trash, p.d_off_scale, p.d_box_scale, nrhs);                      \
+    } else {                                                                                   \
+      UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD, false>), cgrid, dim3(kBlock), s,   \
+                 tb, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,     \
+                 p.n_pairs(), trash, p.d_off_scale, p.d_box_scale, nrhs);                      \
+    }                                                                                          \
+  } while (0)
 #define UBF_SPLIT_NU(F16, NPROD)                           \
   switch (p.nu) {                                          \
     case 81: UBF_SPLIT(81, F16, NPROD); break;             \

@@ -308,6 +308,40 @@ void partition_groups(Plan& P, int64_t groups) {
   for (int64_t g = 1; g < groups; ++g) P.wg_ptr[g] = (int32_t)((nch * g + groups - 1) / groups);
 }
 
+void build_rounds(Plan& P, int64_t groups) {
+  const int64_t ni = P.n_items();
+  groups = std::min<int64_t>(groups, std::max<int64_t>(ni, 1));
+  groups = std::min<int64_t>((groups + 7) / 8 * 8, kMaxTranslateGroups);
+  P.rounds.clear();
+  P.wg_round_ptr.assign(groups + 1, 0);
+  const int32_t* it = P.items.data();
+  for (int64_t g = 0; g < groups; ++g) {
+    const int64_t ib = ni * g / groups, ie = ni * (g + 1) / groups;
+    for (int64_t i = ib; i < ie;) {
+      const int32_t o = it[4 * i];
+      int64_t j = i;
+      while (j < ie && it[4 * j] == o) ++j;
+      const int32_t next = j < ie ? it[4 * j] + 1 : 0;  // next segment's offset + 1
+      for (int64_t r = i; r < j; r += 4)
+        for (int w = 0; w < 4; ++w) {
+          const int64_t q = r + w;
+          P.rounds.push_back(o);
+          P.rounds.push_back(q < j ? it[4 * q + 1] : 0);
+          P.rounds.push_back(q < j ? it[4 * q + 2] : 0);
+          P.rounds.push_back(r == i ? (1 | (next << 1)) : 0);
+        }
+      i = j;
+    }
+    P.wg_round_ptr[g + 1] = (int32_t)(P.rounds.size() / 16);
+  }
+}
+
+int64_t max_rounds(const Plan& p) {
+  // ceil(items / 4) rounds, plus at most one partial round per segment;
+  // segments are runs of one offset cut at most once per workgroup
+  return p.n_items() / 4 + p.n_off() + kMaxTranslateGroups + 1;
+}
+
 Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   Layout L{};
   size_t at = 0;
@@ -320,6 +354,8 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   L.chunks = take(p.chunks.size() * sizeof(int32_t));
   L.items = take(p.items.size() * sizeof(int32_t));
   L.wg_ptr = take((size_t)(kMaxTranslateGroups + 1) * sizeof(int32_t));
+  L.rounds = take((size_t)max_rounds(p) * 16 * sizeof(int32_t));
+  L.wg_round_ptr = take((size_t)(kMaxTranslateGroups + 1) * sizeof(int32_t));
   L.pair_src = take(p.pair_src.size() * sizeof(int32_t));
   L.pair_dst = take(p.pair_dst.size() * sizeof(int32_t));
   L.test_ptr = take(p.test_ptr.size() * sizeof(int32_t));
@@ -524,6 +560,7 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
     }
 
   partition_groups(P, kTranslateGroups);
+  build_rounds(P, kRoundGroups);
 
   // Orbits under the 48 signed permutations: key = sorted |w|.
   std::vector<std::array<int32_t, 3>> keys(n_off);

@@ -16,6 +16,18 @@ namespace ubf {
 constexpr int kChunk = 128;
 // Translation workgroups: two resident per compute unit on 256 CUs.
 constexpr int kTranslateGroups = 512;
+// Stage-2 kernels of the 16-bit forms, chosen per plan (ubf_plan_tune or
+// ubf_plan_schedule): persistent workgroups over chunks of 128 pairs, one
+// right-hand side per grid row (kSplitChunks) or every right-hand side of a
+// chunk in turn (kSplitChunksWalk, one operator staging for all of them);
+// rounds of four 32-pair items per workgroup, two workgroups per compute
+// unit with one operator buffer each (kSplitRounds) or one with two buffers
+// and the next operator copied ahead (kSplitRoundsDouble). All give the
+// same result bit for bit.
+enum SplitKernel { kSplitChunks = 0, kSplitChunksWalk = 1, kSplitRounds = 2,
+                   kSplitRoundsDouble = 3 };
+// Default workgroups of the round kernels: two per compute unit.
+constexpr int kRoundGroups = 512;
 // Largest persistent grid the tuner may pick (workspace room for its
 // chunk ranges is reserved at this size).
 constexpr int kMaxTranslateGroups = 4096;
@@ -121,6 +133,16 @@ struct Plan {
   // up to 32 consecutive pairs of one offset: offset, first pair, count, 0.
   std::vector<int32_t> items;
   std::vector<int32_t> wg_ptr;     // chunk range of each translation workgroup
+  // Rounds of the 16-bit translation (one workgroup of four wavefronts per
+  // compute unit): each workgroup walks a contiguous range of items in
+  // rounds; round k gives wavefront w the item (offset, first pair, count,
+  // flags) at rounds[4 * (4 k + w)]; an empty slot has count 0. A round that
+  // starts a run of one offset (a segment) has flags bit 0 set and carries
+  // the offset of the workgroup's next segment plus one in bits 1.. (0: none).
+  std::vector<int32_t> rounds;
+  std::vector<int32_t> wg_round_ptr;  // round range of each workgroup
+  // Stage-2 kernel of the 16-bit forms (enum SplitKernel).
+  int split_kernel = kSplitChunks;
   int32_t n_orbits = 0;
 
   // Operator table image: per offset two planes (re, im) of nu rows of kh
@@ -143,6 +165,7 @@ struct Plan {
   int64_t n_chunks() const { return (int64_t)(chunks.size() / 4); }
   int64_t n_items() const { return (int64_t)(items.size() / 4); }
   int32_t n_groups() const { return (int32_t)wg_ptr.size() - 1; }
+  int32_t n_round_groups() const { return (int32_t)wg_round_ptr.size() - 1; }
   int32_t n_scat() const { return (int32_t)scat_ptr.size() - 1; }
   size_t plane_floats() const { return (size_t)nu * kh; }
   size_t op_floats() const { return 2 * plane_floats(); }
@@ -169,6 +192,8 @@ struct Plan {
   int32_t* d_chunks = nullptr;
   int32_t* d_items = nullptr;
   int32_t* d_wg_ptr = nullptr;
+  int32_t* d_rounds = nullptr;
+  int32_t* d_wg_round_ptr = nullptr;
   int32_t* d_pair_src = nullptr;
   int32_t* d_test_ptr = nullptr;
   int32_t* d_pair_dst = nullptr;
@@ -195,8 +220,8 @@ struct Plan {
 
 // Workspace layout, in bytes from the workspace start.
 struct Layout {
-  size_t table, chunks, items, wg_ptr, pair_src, pair_dst, test_ptr, nb_ptr, P, part, off_scale,
-      box_scale, total;
+  size_t table, chunks, items, wg_ptr, rounds, wg_round_ptr, pair_src, pair_dst, test_ptr, nb_ptr,
+      P, part, off_scale, box_scale, total;
 };
 Layout workspace_layout(const Plan& p, int32_t max_nrhs);
 
@@ -215,6 +240,14 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
                        double k, double eta, int n_d, int far_mode,
                        int precision, const int64_t* scat_ptr, int64_t n_scat,
                        Plan& out);
+
+// Rounds of the 16-bit translation for `groups` workgroups (rounded up to a
+// multiple of 8, at most kMaxTranslateGroups, at most one per item), each
+// taking a contiguous range of items balanced by count; rewrites p.rounds
+// and p.wg_round_ptr.
+void build_rounds(Plan& p, int64_t groups);
+// Upper bound of the round count over every group count build_rounds takes.
+int64_t max_rounds(const Plan& p);
 
 // Contiguous chunk ranges for `groups` persistent translation workgroups
 // (rounded up to a multiple of 8, at most kMaxTranslateGroups), balanced by

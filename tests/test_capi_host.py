@@ -18,7 +18,7 @@ A, K = 0.25, 2 * np.pi
 def test_library_exports_every_declared_symbol():
     L = U.lib()
     names = U.declared_symbols()
-    assert len(names) == 33
+    assert len(names) == 34
     for name in names:
         assert hasattr(L, name), name
 

@@ -127,6 +127,74 @@ def test_tune_keeps_results(precision):
     assert np.array_equal(y0, y1)
 
 
+@pytest.mark.parametrize("precision", ["split-fp16", "split-bf16", "fp16"])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_every_stage2_schedule_gives_the_same_bits(precision, nrhs):
+    # every kernel and grid the tuner may choose computes each column with
+    # the same products in the same order: results agree bit for bit, and
+    # with the oracle (sampled test boxes)
+    w = W.config(2)
+    announce("schedules", w.name, precision, "nrhs", nrhs)
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, max_nrhs=nrhs, precision=precision)
+    x = W.complex_normal((nrhs, ff.nb_total), 17)
+    xd = to_dev(x)
+    y0 = to_host(ff(xd))
+    assert ff.info["translate_kernel"] == U.TRANSLATE_CHUNKS
+    seen = []
+    for kernel, groups in [(U.TRANSLATE_CHUNKS, 256), (U.TRANSLATE_CHUNKS, 4096),
+                           (U.TRANSLATE_CHUNKS_WALK, 512), (U.TRANSLATE_ROUNDS, 512),
+                           (U.TRANSLATE_ROUNDS, 1024), (U.TRANSLATE_ROUNDS_DOUBLE, 256),
+                           (U.TRANSLATE_ROUNDS_DOUBLE, 8)]:
+        ff.schedule(kernel, groups)
+        assert ff.info["translate_kernel"] == kernel
+        y = to_host(ff(xd))
+        assert np.array_equal(y, y0), (kernel, groups)
+        seen.append((kernel, ff.info["translate_groups"]))
+    assert len(set(seen)) == len(seen)
+    sample = np.sort(np.random.default_rng(3).choice(w.n_box, size=40, replace=False))
+    P = x.reshape(nrhs, w.n_box, w.n_u).astype(np.complex128)
+    ref = O.translate(P, w.boxes, w.a, w.k, w.n_d, test_boxes=sample)
+    parity(y0.reshape(nrhs, w.n_box, w.n_u)[:, sample], ref[:, sample],
+           1e-4 if precision != "fp16" else 1e-3, boxes=w.n_u,
+           box_tol=1e-4 if precision != "fp16" else 3e-3, label=f"schedules {precision}")
+    with pytest.raises(U.UbfError):
+        ff.schedule(7, 512)
+    ff.close()
+
+
+def test_fp32_plan_has_only_the_chunk_kernel():
+    w = W.config(1)
+    announce("fp32 schedule")
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d)
+    ff.schedule(U.TRANSLATE_CHUNKS, 256)
+    assert ff.info["translate_groups"] <= 256
+    with pytest.raises(U.UbfError) as e:
+        ff.schedule(U.TRANSLATE_ROUNDS, 512)
+    assert e.value.status == -1
+    ff.close()
+
+
+def test_tune_cache_is_reused(tmp_path, monkeypatch):
+    w = W.config(2)
+    announce("tune cache", w.name)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("UBF_TUNE_CACHE", str(cache))
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, max_nrhs=1, precision="split-fp16")
+    x = to_dev(W.complex_normal((1, ff.nb_total), 5))
+    y0 = to_host(ff(x))
+    g = ff.tune(nrhs=1, reps=2)
+    kernel = ff.info["translate_kernel"]
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split("\t")[1].split()[:2] == [str(kernel), str(g)]
+    # a second plan of the same statistics takes the cached schedule
+    ff2 = U.FarField(w.boxes, w.a, w.k, w.n_d, max_nrhs=1, precision="split-fp16")
+    assert ff2.tune(nrhs=1, reps=2) == g and ff2.info["translate_kernel"] == kernel
+    assert len(cache.read_text().splitlines()) == 1
+    assert np.array_equal(to_host(ff2(x)), y0)
+    ff.close()
+    ff2.close()
+
+
 def test_batch64_full_size_against_solo_and_oracle():
     """64 scatterers (200 to 20k boxes), 4 right-hand sides, split precision,
     tuned and replayed from a graph: the benchmarked batch."""
