@@ -322,6 +322,13 @@ def bench_networks(args, U, W, torch):
     dt, avg_us, lat, y_net = timed()
     ff.set_networks()
     dt_t, avg_t, lat_t, y_table = timed()
+    # the same operator table in split FP16 (three products on the 16-bit
+    # matrix cores, box vectors staged in LDS)
+    ff_fp32 = ff
+    ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, precision="split-fp16")
+    dt_s, avg_s, lat_s, y_split = timed()
+    ff.close()
+    ff = ff_fp32
     info = ff.info
     n_pairs, nu = info["n_pairs"], info["n_u"]
     flops = 16.0 * hidden * nu * n_pairs          # two complex layers per pair
@@ -359,6 +366,13 @@ def bench_networks(args, U, W, torch):
                     "value": args.steps / dt_t, "translate_us": float(avg_t[1]),
                     "speedup_of_networks": dt_t / dt,
                     "translate_speedup_of_networks": float(avg_t[1] / avg_us[1])},
+        "compare_split_fp16": {
+            "translation": "operator table, split FP16 (three products on the FP16 matrix "
+                           "cores, box vectors staged in LDS)",
+            "value": args.steps / dt_s, "translate_us": float(avg_s[1]),
+            "stages_us": [float(v) for v in avg_s],
+            "speedup_over_fp32_table": dt_t / dt_s,
+            "translate_speedup_over_fp32_table": float(avg_t[1] / avg_s[1])},
     }
     out["stages"]["translate"].update(kernel="translate_cvfcnn", algorithmic_flops=flops,
                                       tflops=tr, issued_flops=issued,
@@ -369,6 +383,10 @@ def bench_networks(args, U, W, torch):
                                         args.cpu_seconds)
         out["cpu_baseline"] = cb
         out.update(acc)
+        import oracle as O
+        y_dgfa = O.far_mvm(x0.astype(np.complex128), w.boxes, w.a, w.k, w.n_d, mode=w.far_mode)
+        out["compare_split_fp16"]["rel_l2_vs_oracle"] = float(
+            np.linalg.norm(y_split - y_dgfa) / np.linalg.norm(y_dgfa))
     ff.close()
     print(json.dumps(out))
     return 0

@@ -76,7 +76,9 @@ enum ubf_precision {
                           into a BF16 high part and a BF16 remainder,
                           G P ~ Gh Ph + Gh Pl + Gl Ph on the BF16 matrix cores
                           with FP32 accumulation (stages 1 and 3 stay FP32);
-                          n_d 1..3 */
+                          n_d 1..4 (at n_d = 4 the operator is stored in
+                          matrix-core fragment order and the item's box
+                          vectors are staged in LDS) */
   UBF_SPLIT_FP16 = 2,  /* as UBF_SPLIT_BF16 with FP16 parts: each operator is
                           stored divided by a power of two (per offset) and
                           each box vector by a power of two (per box and
@@ -153,9 +155,9 @@ typedef struct ubf_plan ubf_plan;
  * orbits (Sec. 2.2), the work partition, and the FP32 operator table
  * from FP64 evaluations of Eq. (5)-(6) and (13).
  * Errors: UBF_EINVAL for a null pointer, n_boxes < 1, a negative or
- * duplicate coordinate, a <= 0, k <= 0, eta < 0, n_d outside 1..4 (1..3
- * for the 16-bit forms), an unknown far_mode or precision, or a far set
- * beyond 2^31-1 pairs;
+ * duplicate coordinate, a <= 0, k <= 0, eta < 0, n_d outside 1..4, an
+ * unknown far_mode or precision, a far set beyond 2^31-1 pairs, or an
+ * operator table beyond 16 GiB;
  * UBF_ENOMEM if host memory runs out. *out is set only on success. */
 int ubf_plan_create(const ubf_problem* problem, ubf_plan** out);
 
@@ -312,8 +314,9 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
  * up to a multiple of 8 and capped by the work units). Uploads the work
  * partition on hip_stream and waits. Results do not depend on the choice.
  * Any captured graph is discarded. Errors: UBF_EINVAL (null plan, unknown
- * kernel, a 16-bit kernel on an FP32 plan, groups out of range),
- * UBF_ESTATE (unbound), UBF_EDEVICE. */
+ * kernel, a 16-bit kernel on an FP32 plan, groups out of range, or a plan
+ * whose stage 2 runs one workgroup per item: networks set, or 192
+ * coefficients per box), UBF_ESTATE (unbound), UBF_EDEVICE. */
 int ubf_plan_schedule(ubf_plan* plan, int32_t kernel, int32_t groups, void* hip_stream);
 
 /* Stage 1 alone: d_P[nrhs][n_boxes][N_u] = S_i x_i (complex64). */

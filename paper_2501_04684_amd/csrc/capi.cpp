@@ -424,6 +424,9 @@ int ubf_plan_schedule(ubf_plan* plan, int32_t kernel, int32_t groups, void* hip_
     return fail(UBF_EINVAL, "only the 16-bit forms have stage-2 kernels other than 0");
   if (groups < 1 || groups > ubf::kMaxTranslateGroups)
     return fail(UBF_EINVAL, "groups must be in 1.." + std::to_string(ubf::kMaxTranslateGroups));
+  if (p.hidden > 0 || ubf::staged_translate_supported(p))
+    return fail(UBF_EINVAL, "this plan's stage 2 (networks, or 192 coefficients per box) runs "
+                            "one workgroup per item and has no schedule to choose");
   plan->drop_graph();
   const int e = apply_schedule(p, kernel, groups, (hipStream_t)hip_stream);
   if (e) return hip_fail(e, "upload (schedule)");

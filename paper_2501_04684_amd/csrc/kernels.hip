@@ -152,23 +152,30 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(
 }
 
 // FP16 forms: one wavefront per box vector (row), four per workgroup; the
-// vector's scale needs its largest component first. nu <= 128.
+// vector's scale needs its largest component first. nu <= 192 (three
+// coefficients per lane).
 __global__ __launch_bounds__(kBlock) void pack_f16_kernel(
     const float2* __restrict__ x, float* __restrict__ P, float* __restrict__ box_scale,
     int nu, int khb, int64_t n_rows) {
   const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (row >= n_rows) return;  // whole wavefronts
   const int l = threadIdx.x & 63;
-  const float2 v0 = l < nu ? x[row * nu + l] : make_float2(0.f, 0.f);
-  const float2 v1 = l + 64 < nu ? x[row * nu + l + 64] : make_float2(0.f, 0.f);
-  float m = fmaxf(fmaxf(fabsf(v0.x), fabsf(v0.y)), fmaxf(fabsf(v1.x), fabsf(v1.y)));
+  float2 v[3];
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int u = l + 64 * i;
+    v[i] = u < nu ? x[row * nu + u] : make_float2(0.f, 0.f);
+    m = fmaxf(m, fmaxf(fabsf(v[i].x), fabsf(v[i].y)));
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   const float sc = box_scale_for(m);
   const float inv = 1.f / sc;
   float* Pb = P + row * 2 * khb;
-  if (l < khb) put_coef(Pb, l, v0.x, v0.y, 0, khb, 2, inv);
-  if (l + 64 < khb) put_coef(Pb, l + 64, v1.x, v1.y, 0, khb, 2, inv);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (l + 64 * i < khb) put_coef(Pb, l + 64 * i, v[i].x, v[i].y, 0, khb, 2, inv);
   if (l == 0) box_scale[row] = sc;
 }
 

@@ -462,6 +462,109 @@ __global__ __launch_bounds__(kBlock, 4) void translate_staged_kernel(
   }
 }
 
+// 16-bit matrix-core product on 8 values per lane (FP32 accumulation).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+template <bool F16>
+__device__ inline floatx16 mfma16(uintx4 a, uintx4 b, floatx16 c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a),
+                                                 __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// The split-precision operator-table product for box sizes whose 16-bit
+// columns do not fit in registers (N_u = 192, the paper's 4x4x4 dipoles),
+// on v_mfma_f32_32x32x16_f16 / _bf16: the same products as the register
+// kernels (G_h P_h + G_h P_l + G_l P_h, or G_h P_h alone), one workgroup per
+// work item (up to 32 pairs of one offset). The item's 16-bit box vectors
+// (stage 1's layout: per k-step of 8 coefficients, [re.hi | im.hi | re.lo |
+// im.lo]) are staged whole in LDS, one column per row with a 16-byte pad so
+// that the 32 columns' reads spread over the banks; wavefront w computes the
+// 32-row blocks w, w + 4, w + 8 of [[Gr, -Gi], [Gi, Gr]] (M = K = 2 N_u),
+// with the A values read from the operator image in matrix-core fragment
+// order (per block, k-step and part: 64 lanes x 16 bytes contiguous). FP16:
+// each result is multiplied by its offset's and its source box's scales
+// (powers of two).
+template <int NU, bool F16, int NPROD>
+__global__ __launch_bounds__(kBlock, 2) void translate_staged_split_kernel(
+    const unsigned short* __restrict__ table, const int32_t* __restrict__ items,
+    const int32_t* __restrict__ pair_src, const int32_t* __restrict__ pair_dst,
+    const float* __restrict__ P, float* __restrict__ part, int64_t n_box, int64_t n_pairs,
+    int n_items, const float* __restrict__ off_scale, const float* __restrict__ box_scale) {
+  constexpr int KH = (NU + 3) & ~3;
+  constexpr int KHB = (NU + 7) & ~7;
+  constexpr int NGB = KHB / 8;            // k-steps per half
+  constexpr int VU = NGB * 4;             // 16-byte units per box vector
+  constexpr int CPU = VU + 1;             // LDS pitch per column (units)
+  constexpr int OB = (2 * NU + 31) / 32;  // 32-row blocks
+  constexpr int PER = (OB + 3) / 4;       // blocks per wavefront
+  constexpr int NPART = NPROD == 3 ? 2 : 1;
+  constexpr int PSTR = 2 * KH;
+  __shared__ uintx4 cols[32 * CPU];
+
+  int o, first, ncol;
+  if (!load_item(items, n_items, o, first, ncol)) return;  // grid padding
+  const int rhs = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const uintx4* Pv = reinterpret_cast<const uintx4*>(P) + (int64_t)rhs * n_box * VU;
+  // stage the item's columns (past ncol: the last pair again)
+  for (int u = threadIdx.x; u < 32 * VU; u += kBlock) {
+    const int c = u / VU, q = u - c * VU;
+    const int src = pair_src[first + min(c, ncol - 1)];
+    cols[c * CPU + q] = Pv[(int64_t)src * VU + q];
+  }
+  const int src_r = pair_src[first + min(r, ncol - 1)];
+  const int dst = pair_dst[first + min(r, ncol - 1)];
+  const float sc = F16 ? off_scale[o] * box_scale[(int64_t)rhs * n_box + src_r] : 1.f;
+  __syncthreads();
+
+  const uintx4* Ao = reinterpret_cast<const uintx4*>(table) + (size_t)o * OB * NGB * NPART * 64;
+  const uintx4* arow[PER];
+  floatx16 acc[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    arow[i] = Ao + (size_t)min(wave + 4 * i, OB - 1) * NGB * NPART * 64 + lane;
+    acc[i] = floatx16{};
+  }
+  const uintx4* col = cols + r * CPU;
+#pragma unroll 4
+  for (int g = 0; g < NGB; ++g) {
+    const uintx4 bh = col[4 * g + h];
+    const uintx4 bl = NPROD == 3 ? col[4 * g + 2 + h] : uintx4{};
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uintx4 ah = arow[i][(g * NPART) * 64];
+      acc[i] = mfma16<F16>(ah, bh, acc[i]);
+      if (NPROD == 3) {
+        const uintx4 al = arow[i][(g * NPART + 1) * 64];
+        acc[i] = mfma16<F16>(ah, bl, acc[i]);
+        acc[i] = mfma16<F16>(al, bh, acc[i]);
+      }
+    }
+  }
+  if (r < ncol) {
+    float* prow = part + ((int64_t)rhs * n_pairs + dst) * PSTR;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int ob = wave + 4 * i;
+      if (ob >= OB) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r0 = ob * 32 + 8 * q + 4 * h;
+        if (r0 < 2 * NU)
+          *reinterpret_cast<floatx4*>(prow + r0) =
+              floatx4{acc[i][4 * q], acc[i][4 * q + 1], acc[i][4 * q + 2], acc[i][4 * q + 3]} *
+              sc;
+      }
+    }
+  }
+}
+
 int grid_for(int64_t total) {
   const int64_t g = (total + kBlock - 1) / kBlock;
   return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
@@ -530,7 +633,7 @@ int launch_translate_cvfcnn(const Plan& p, const float* P, float* part, int nrhs
   return (int)hipGetLastError();
 }
 
-bool staged_translate_supported(const Plan& p) { return !p.split() && p.nu == 192; }
+bool staged_translate_supported(const Plan& p) { return p.nu == 192; }
 
 int launch_translate_staged(const Plan& p, const float* P, float* part, int nrhs, void* stream,
                             const StageEvents* ev) {
@@ -545,10 +648,22 @@ int launch_translate_staged(const Plan& p, const float* P, float* part, int nrhs
     }
     return 0;
   }
-  if (p.nu != 192 || p.split()) return (int)hipErrorInvalidValue;
-  UBF_LAUNCH(t0, t1, translate_staged_kernel<192>, dim3((unsigned)((nit + 7) / 8 * 8), nrhs),
-             s, p.d_table, p.d_items, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,
-             p.n_pairs(), nit);
+  if (p.nu != 192) return (int)hipErrorInvalidValue;
+  const dim3 grid((unsigned)((nit + 7) / 8 * 8), nrhs);
+  if (!p.split()) {
+    UBF_LAUNCH(t0, t1, translate_staged_kernel<192>, grid, s, p.d_table, p.d_items,
+               p.d_pair_src, p.d_pair_dst, P, part, p.n_box, p.n_pairs(), nit);
+    return (int)hipGetLastError();
+  }
+  const unsigned short* tb = reinterpret_cast<const unsigned short*>(p.d_table);
+#define UBF_STAGED16(F16, NPROD)                                                             \
+  UBF_LAUNCH(t0, t1, (translate_staged_split_kernel<192, F16, NPROD>), grid, s, tb, p.d_items, \
+             p.d_pair_src, p.d_pair_dst, P, part, p.n_box, p.n_pairs(), nit, p.d_off_scale,    \
+             p.d_box_scale)
+  if (p.precision == 1) UBF_STAGED16(false, 3);
+  else if (p.precision == 2) UBF_STAGED16(true, 3);
+  else UBF_STAGED16(true, 1);
+#undef UBF_STAGED16
   return (int)hipGetLastError();
 }
 #undef UBF_LAUNCH

@@ -95,10 +95,58 @@ int64_t floordiv2(int64_t c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
 // nu rows of kh floats. Split: G is rounded to FP32 first (as in the FP32
 // path), then hi = bf16(G), lo = bf16(G - hi); planes re.hi, im.hi, re.lo,
 // im.lo of nu rows of khb values. Padding columns are zero.
+// The 16-bit image of 192-coefficient boxes, in the matrix-core fragment
+// order of the staged split kernel: per 32-row block b of the real form
+// [[Gr, -Gi], [Gi, Gr]], k-step g (8 values of each K half) and part (hi,
+// then lo unless the single-product form), 64 lanes x 8 values: lane l holds
+// row 32 b + l % 32 and K half l / 32 (the real inputs for 0, the imaginary
+// ones for 1), values k = 8 g .. 8 g + 7. Each operator value v (divided by
+// the offset's power-of-two scale in the FP16 forms) is hi = round16(v),
+// lo = round16(v - hi), as in the plane layout.
+void staged_split_image(const Plan& P, const std::vector<std::complex<double>>& G, double inv,
+                        uint16_t* out) {
+  const int nb = (2 * P.nu + 31) / 32, ng = P.khb / 8, np = P.precision == 3 ? 1 : 2;
+  for (int b = 0; b < nb; ++b)
+    for (int g = 0; g < ng; ++g)
+      for (int q = 0; q < np; ++q)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 8; ++j) {
+            const int row = 32 * b + (l & 31), h = l >> 5, k = 8 * g + j;
+            double v = 0.0;
+            if (row < 2 * P.nu && k < P.nu) {
+              const bool ei = row >= P.nu;
+              const std::complex<double> c = G[(size_t)(ei ? row - P.nu : row) * P.nu + k];
+              v = !ei ? (h == 0 ? c.real() : -c.imag()) : (h == 0 ? c.imag() : c.real());
+            }
+            const float f = (float)(v * inv);
+            uint16_t bits;
+            if (P.fp16()) {
+              const uint16_t hi = fp16_bits(f);
+              bits = q == 0 ? hi : fp16_bits(f - fp16_value(hi));
+            } else {
+              const uint16_t hi = bf16_bits(f);
+              bits = q == 0 ? hi : bf16_bits(f - bf16_value(hi));
+            }
+            out[((((size_t)b * ng + g) * np + q) * 64 + l) * 8 + j] = bits;
+          }
+}
+
 void offset_image(const Plan& P, const int32_t* w, std::vector<std::complex<double>>& G,
                   char* dst, float* scale) {
   operator_fp64(w, P.a, P.k, P.eta, P.n_d, G);
   *scale = 1.0f;
+  if (P.staged_split()) {
+    double inv = 1.0;
+    if (P.fp16()) {  // power of two bringing the largest |Re|, |Im| to [2^14, 2^15)
+      double mx = 0.0;
+      for (const auto& g : G) mx = std::max({mx, std::abs(g.real()), std::abs(g.imag())});
+      const int e = mx > 0.0 ? std::ilogb(mx) - 14 : 0;
+      *scale = (float)std::ldexp(1.0, e);
+      inv = std::ldexp(1.0, -e);  // exact power of two
+    }
+    staged_split_image(P, G, inv, (uint16_t*)dst);
+    return;
+  }
   if (P.fp16()) {
     // power of two bringing the largest |Re|, |Im| to [2^14, 2^15)
     double mx = 0.0;
@@ -397,7 +445,6 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   if (n_d < 1 || n_d > 4) return "n_d must be in 1..4";
   if (far_mode != 0 && far_mode != 1) return "unknown far_mode";
   if (precision < 0 || precision > 3) return "unknown precision";
-  if (precision >= 1 && n_d > 3) return "split precision supports n_d 1..3";
 
   P.n_box = n_box;
   P.boxes.assign(box_ijk, box_ijk + 3 * n_box);
@@ -506,10 +553,13 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
     for (int64_t p = 0; p < np; ++p) oid[p] = rank[oid[p]];
   }
   const int64_t n_off = (int64_t)uniq.size();
-  const double table_bytes = precision == 1
-      ? (double)n_off * 4.0 * P.nu * half_len_bf16(P.nu) * sizeof(uint16_t)
-      : (double)n_off * 2.0 * P.nu * P.kh * sizeof(float);
-  if (table_bytes > kMaxTableBytes) return "operator table would exceed 16 GiB";
+  // bytes of one offset's image in the table layout of the plan's form
+  const size_t img_bytes = P.staged_split() ? P.staged_split_halves() * sizeof(uint16_t)
+                           : P.split()        ? (size_t)4 * P.nu * P.khb * sizeof(uint16_t)
+                           : P.staged()       ? P.staged_op_floats() * sizeof(float)
+                                              : (size_t)2 * P.nu * P.kh * sizeof(float);
+  if ((double)n_off * (double)img_bytes > kMaxTableBytes)
+    return "operator table would exceed 16 GiB";
   P.offsets.resize(3 * n_off);
   for (int64_t o = 0; o < n_off; ++o)
     for (int d = 0; d < 3; ++d) P.offsets[3 * o + d] = uniq[o][d];
@@ -574,9 +624,6 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   P.n_orbits = (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
 
   // Operator table image, one offset at a time (cached across plans).
-  const size_t img_bytes = P.split()    ? (size_t)4 * P.nu * P.khb * sizeof(uint16_t)
-                           : P.staged() ? P.staged_op_floats() * sizeof(float)
-                                        : (size_t)2 * P.nu * P.kh * sizeof(float);
   if (P.split())
     P.table_bf16.assign((size_t)n_off * img_bytes / sizeof(uint16_t), 0);
   else

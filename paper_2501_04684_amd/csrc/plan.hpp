@@ -175,6 +175,13 @@ struct Plan {
   // k-steps, 64 lanes x 4 floats.
   bool staged() const { return !split() && nu == 192; }
   size_t staged_op_floats() const { return (size_t)((2 * nu + 31) / 32) * (kh / 4) * 256; }
+  // 16-bit operators of 192-coefficient boxes are stored in the fragment
+  // order of the staged split kernel: per 32-row block, k-step of 8 and part
+  // (hi, lo; hi only for the single-product form), 64 lanes x 8 values.
+  bool staged_split() const { return split() && nu == 192; }
+  size_t staged_split_halves() const {
+    return (size_t)((2 * nu + 31) / 32) * (khb / 8) * (precision == 3 ? 1 : 2) * 64 * 8;
+  }
   int pstride() const { return 2 * kh; }              // partial rows, floats
   // Box vectors of stage 1 -> 2, in floats: FP32 [re | im] halves, or in
   // split mode [re: hi, lo | im: hi, lo] BF16 runs of khb values.

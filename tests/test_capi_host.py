@@ -294,9 +294,17 @@ def test_split_precision_plan():
         assert info["table_bytes"] == info["n_offsets"] * 4 * 81 * 88 * 2
     finally:
         U.plan_destroy(plan)
-    with pytest.raises(U.UbfError) as e:
-        U.plan_create(b, A, K, 4, "ilist", precision="split-bf16")
-    assert "split precision" in str(e.value)
+    # 192 coefficients per box (the paper's 4x4x4 dipoles): the operator in
+    # the staged kernel's fragment order, 12 row blocks x 24 k-steps x (hi,
+    # lo) x 64 lanes x 8 values; the single FP16 product keeps hi only
+    for form, parts in (("split-bf16", 2), ("split-fp16", 2), ("fp16", 1)):
+        plan = U.plan_create(b, 0.125, K, 4, "ilist", precision=form)
+        try:
+            info = U.plan_info(plan)
+            assert info["n_u"] == 192 and info["mfma"] == 1
+            assert info["table_bytes"] == info["n_offsets"] * 12 * 24 * parts * 64 * 8 * 2
+        finally:
+            U.plan_destroy(plan)
 
 
 def _small_scatterers():
@@ -444,8 +452,8 @@ def test_fp16_plans(form, code):
         assert info["table_bytes"] == info["n_offsets"] * 4 * 81 * 88 * 2
     finally:
         U.plan_destroy(plan)
-    with pytest.raises(U.UbfError):
-        U.plan_create(b, A, K, 4, "ilist", precision=form)
+    # n_d = 4 is accepted in every form (see test_split_precision_plan);
+    # an unknown precision code is refused
     bb = np.ascontiguousarray(b.astype(np.int32))
     prob = U._Problem(len(bb), bb.ctypes.data, A, K, 0.0, 3, 0, 4)
     out = ctypes.c_void_p()

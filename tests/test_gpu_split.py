@@ -137,3 +137,36 @@ def test_wide_dynamic_range_across_boxes(form, tol):
     scale = contribution_scale(P, w.boxes, w.a, w.k, w.n_d)[0]
     parity(E, ref, tol, boxes=w.n_u, box_scale=scale, label=f"{form} dynamic range",
            box_tol=tol)
+
+
+@pytest.mark.parametrize("form,tol", FORMS)
+@pytest.mark.parametrize("case", ["grid4", "grid445", "sphere762"])
+def test_split_nd4_paper_box_size(case, form, tol):
+    """4x4x4 dipoles (192 coefficients per box), the paper's box of Sec. 3
+    and the sphere examples of Sec. 5: the 16-bit products with the box
+    vectors staged in LDS, against the oracle, two right-hand sides; the
+    762-box sphere at a = 0.125 is the workload the network benchmark uses."""
+    if case == "sphere762":
+        w = W.config(6, nrhs=2)
+        boxes, a = w.boxes, w.a
+    else:
+        boxes = W.grid_boxes(4, 4, 4) if case == "grid4" else W.grid_boxes(4, 4, 5)
+        a = 0.125
+    announce("split n_d=4", case, len(boxes), form)
+    ff = U.FarField(boxes, a, 2 * np.pi, 4, "ilist", max_nrhs=2, precision=form)
+    assert ff.info["n_u"] == 192 and ff.info["mfma"] == 1
+    x = W.complex_normal((2, len(boxes) * 192), 44)
+    x[1, 3 * 192:4 * 192] = 0                     # a zero box vector (scale 1)
+    y = to_host(ff(to_dev(x)))
+    ref = O.far_mvm(x.astype(np.complex128), boxes, a, 2 * np.pi, 4)
+    parity(y, ref, tol, boxes=192, box_tol=BOX_TOL[form], label=f"n_d=4 {case} {form}")
+    # stage 2 alone (box vectors packed from complex64 input)
+    P = x.reshape(2, len(boxes), 192)
+    Pd = to_dev(P)
+    Ed = torch.empty_like(Pd)
+    U.translate(ff.plan, Pd, Ed, 2)
+    parity(to_host(Ed), ref.reshape(2, len(boxes), 192), tol, boxes=192,
+           box_tol=BOX_TOL[form], label=f"n_d=4 {case} {form} stage 2")
+    # deterministic
+    assert np.array_equal(to_host(ff(to_dev(x))), y)
+    ff.close()
