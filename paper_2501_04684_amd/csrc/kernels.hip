@@ -551,8 +551,9 @@ __device__ inline void wait_vmcnt() {
 // may be overwritten afterwards). Unlike __syncthreads it does not wait for
 // outstanding global loads and stores.
 __device__ inline void lds_reads_done_barrier() {
-  __builtin_amdgcn_s_waitcnt((0xF) | (0x3 << 14) | (0x7 << 4) | (0x0 << 8));  // lgkmcnt(0)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Workgroup barrier after each wavefront has waited for its own direct
@@ -579,6 +580,34 @@ __device__ inline void copy_to_lds(const uintx4* __restrict__ src, uintx4* dst) 
         (__attribute__((address_space(3))) void*)(dst + it * kBlock + wave * 64), 16, 0, 0);
 }
 
+// 32-bit LDS address of a pointer into __shared__ memory.
+__device__ inline unsigned lds_address(const float* p) {
+  return (unsigned)reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) float*)p);
+}
+
+// One transpose step of a wavefront's tile: writes this lane's four 16-byte
+// pieces (one column, rows 8 q .. 8 q + 3 for q = 0..3, at `waddr`), then
+// reads four pieces 8 tile rows apart (at `raddr`) and waits for them, all
+// in one statement. Written out so that the compiler does not make these
+// accesses wait for a direct copy into another LDS buffer still in flight.
+__device__ inline void transpose_tile(unsigned waddr, unsigned raddr, floatx4 w0, floatx4 w1,
+                                      floatx4 w2, floatx4 w3, floatx4 (&v)[4]) {
+  static_assert(kTilePitch * 4 * 8 == 1152, "tile row offsets");
+  asm volatile(
+      "ds_write_b128 %4, %6\n\t"
+      "ds_write_b128 %4, %7 offset:32\n\t"
+      "ds_write_b128 %4, %8 offset:64\n\t"
+      "ds_write_b128 %4, %9 offset:96\n\t"
+      "ds_read_b128 %0, %5\n\t"
+      "ds_read_b128 %1, %5 offset:1152\n\t"
+      "ds_read_b128 %2, %5 offset:2304\n\t"
+      "ds_read_b128 %3, %5 offset:3456\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3])
+      : "v"(waddr), "v"(raddr), "v"(w0), "v"(w1), "v"(w2), "v"(w3)
+      : "memory");
+}
+
 // Split-precision translation on the 16-bit matrix cores
 // (v_mfma_f32_32x32x16_bf16 / _f16, FP32 accumulation). With G = Gh + Gl
 // and P = Ph + Pl (h = the value rounded to 16 bits, l = the remainder
@@ -597,14 +626,21 @@ __device__ inline void copy_to_lds(const uintx4* __restrict__ src, uintx4* dst) 
 // adjacent 16 bytes); -Gi is a sign flip of the A values; 32-row blocks
 // cover all 2*NU rows (padding rows read row 0 and are not stored).
 //
+// Per unit (a chunk, and with WALK one of its right-hand sides): pass 1 runs
+// Gh Ph and Gh Pl over all k-steps, pass 2 runs Gl Ph and, k-step by
+// k-step, refills the column registers with the next unit's box vector.
 // The operator's planes are stored hi half first ([re.hi | im.hi] then
-// [re.lo | im.lo]) and copied straight into LDS. The hi half is waited for
-// first: pass 1 runs Gh Ph and Gh Pl over all k-steps while the lo half is
-// still arriving, pass 2 runs Gl Ph (and refills the registers with the next
-// chunk's columns). Partial rows leave through a per-wavefront LDS tile:
-// each block is written as 4-row pieces per column, read back as 8 columns
-// x 128 contiguous bytes per store instruction, the destination rows taken
-// once per chunk from their owner lanes.
+// [re.lo | im.lo]) and copied global -> LDS directly: the first one before
+// the loop, each later one (when the next unit has another offset) after
+// every wavefront has finished pass 2 and before the partial rows leave, so
+// that the copy and the stores are in flight together; the next unit waits
+// for the copy alone (the stores issued after it may still be in flight).
+// Partial rows leave through a per-wavefront LDS tile: each block is
+// written as 4-row pieces per column and read back as 8 columns x 128
+// contiguous bytes per store instruction, the destination rows taken once
+// per unit from their owner lanes; every wavefront issues the same number
+// of stores (absent columns and padding rows go to the spare row), which
+// the wait for the copy counts on.
 template <int NU, bool F16, int NPROD, bool WALK>
 __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const unsigned short* __restrict__ table, const int32_t* __restrict__ chunks,
@@ -657,62 +693,53 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   const int col0 = wave * 32;
   const int64_t last = n_pairs - 1;
 
-  // Unconditional memory operations, pair indices two units ahead, B
-  // values one unit ahead (refilled in pass 2).
+  // Unconditional memory operations: pair indices one unit ahead, B values
+  // one unit ahead (refilled in pass 2), the next operator copied straight
+  // into LDS before the partial rows leave.
   auto unit_rhs = [&](int v) { return WALK ? v % nv : (int)blockIdx.y; };
-  int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
+  int o0 = chunks[4 * cbeg], n0 = chunks[4 * cbeg + 2];
   int rhs0 = unit_rhs(vbeg);
-  const bool has1 = vbeg + 1 < vend;
-  const int c1 = (vbeg + 1) / nv;
-  int rhs1 = has1 ? unit_rhs(vbeg + 1) : rhs0;
-  int o1 = has1 ? chunks[4 * c1] : o0;
-  int b1 = has1 ? chunks[4 * c1 + 1] : 0;
-  int n1 = has1 ? chunks[4 * c1 + 2] : 0;
-  int64_t i0 = min((int64_t)b0 + col0 + r, last), i1 = min((int64_t)b1 + col0 + r, last);
-  int src0 = pair_src[i0], dst0 = pair_dst[i0];
-  int src1 = pair_src[i1], dst1 = pair_dst[i1];
-
-  // k-step g of a box vector is 64 bytes: hi of both halves, then lo of both
+  int dst0;
   vec16 bh[NGB], bl[NPROD == 3 ? NGB : 1];
+  float bsc0 = 1.f;
   {
+    const int64_t i0 = min((int64_t)chunks[4 * cbeg + 1] + col0 + r, last);
+    const int src0 = pair_src[i0];
+    dst0 = pair_dst[i0];
+    // k-step g of a box vector is 64 bytes: hi of both halves, then lo of both
     const vec16* pv = reinterpret_cast<const vec16*>(P + ((int64_t)rhs0 * n_box + src0) * VSTR);
 #pragma unroll
     for (int g = 0; g < NGB; ++g) {
       bh[g] = pv[4 * g + h];
       if (NPROD == 3) bl[g] = pv[4 * g + 2 + h];
     }
+    // FP16: the scale of the current chunk's column (this lane's source box)
+    if (F16) bsc0 = box_scale[(int64_t)rhs0 * n_box + src0];
   }
-  // FP16: the scale of the current chunk's column (this lane's source box)
-  float bsc0 = F16 ? box_scale[(int64_t)rhs0 * n_box + src0] : 1.f, bsc1 = 1.f;
+  const uintx4* gt = reinterpret_cast<const uintx4*>(table);
+  constexpr size_t OPU = 4 * PLANE / 8;  // 16-byte units per operator
+  copy_to_lds<H16>(gt + (size_t)o0 * OPU, lds4);
+  if (NPROD == 3) copy_to_lds<H16>(gt + (size_t)o0 * OPU + H16, lds4 + HPAD);
+  wait_vmcnt<0>();
+  lds_copies_done_barrier();
 
-  int staged = -1;
+  bool pending = false;
   for (int v = vbeg; v < vend; ++v) {
-    const bool restage = o0 != staged;  // uniform across the workgroup
-    if (restage) {
-      // both halves through registers: the hi half's units, then the lo half's
-      constexpr int NH = NPROD == 3 ? 2 : 1;
-      const uintx4* g4 = reinterpret_cast<const uintx4*>(table + (size_t)o0 * 4 * PLANE);
-      uintx4 tmp[NH * NLD];
-#pragma unroll
-      for (int hh = 0; hh < NH; ++hh)
-#pragma unroll
-        for (int it = 0; it < NLD; ++it)
-          tmp[hh * NLD + it] = g4[hh * H16 + min((int)threadIdx.x + it * kBlock, H16 - 1)];
-      __syncthreads();  // every wavefront is done with the previous operator
-#pragma unroll
-      for (int hh = 0; hh < NH; ++hh)
-#pragma unroll
-        for (int it = 0; it < NLD; ++it) lds4[hh * HPAD + threadIdx.x + it * kBlock] = tmp[hh * NLD + it];
-      __syncthreads();
-      staged = o0;
+    if (pending) {
+      // the copy was issued just before the previous unit's RB * 4 stores
+      wait_vmcnt<RB * 4>();
+      lds_copies_done_barrier();
+      pending = false;
     }
-    const bool has2 = v + 2 < vend;
-    const int c2 = (v + 2) / nv;
-    const int rhs2 = has2 ? unit_rhs(v + 2) : rhs1;
-    const int o2 = has2 ? chunks[4 * c2] : o1;
-    const int b2 = has2 ? chunks[4 * c2 + 1] : 0;
-    const int n2 = has2 ? chunks[4 * c2 + 2] : 0;
-    const int64_t i2 = min((int64_t)b2 + col0 + r, last);
+    const bool has1 = v + 1 < vend;
+    const int c1 = (v + 1) / nv;
+    const int rhs1 = has1 ? unit_rhs(v + 1) : rhs0;
+    const int o1 = has1 ? chunks[4 * c1] : o0;
+    const int b1 = has1 ? chunks[4 * c1 + 1] : 0;
+    const int n1 = has1 ? chunks[4 * c1 + 2] : 0;
+    const int64_t i1 = min((int64_t)b1 + col0 + r, last);
+    const int src1 = pair_src[i1];
+    const int dst1 = pair_dst[i1];
     const bool active = col0 < n0;  // wave-uniform
 
     floatx16 acc[RB];
@@ -737,15 +764,17 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
         }
       }
     }
-    // the next chunk's column (its index arrived long ago): its box vector
-    // is fetched in pass 2, its FP16 scale here
+    // the next unit's column: its box vector is fetched in pass 2, its FP16
+    // scale here
     const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs1 * n_box + src1) * VSTR);
-    if (F16) bsc1 = box_scale[(int64_t)rhs1 * n_box + src1];
-    if (active) {
-      // pass 2: Gl Ph, refilling the registers with the next chunk's columns
+    const float bsc1 = F16 ? box_scale[(int64_t)rhs1 * n_box + src1] : 1.f;
+    // pass 2: Gl Ph, refilling the registers with the next unit's columns
+    // (the test is per k-step so that each refill stays next to its k-step's
+    // products instead of being gathered after the pass)
 #pragma unroll
-      for (int g = 0; g < NGB; ++g) {
-        if (NPROD == 3) {
+    for (int g = 0; g < NGB; ++g) {
+      if (NPROD == 3) {
+        if (active) {
           vec16 a_l[RB];
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
@@ -755,24 +784,25 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
           }
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) acc[rb] = Mfma16<F16>::run(a_l[rb], bh[g], acc[rb]);
-          bl[g] = pv1[4 * g + 2 + h];
         }
-        bh[g] = pv1[4 * g + h];
+        bl[g] = pv1[4 * g + 2 + h];
       }
-    } else {  // no column of this chunk for this wavefront: fetch the next
-#pragma unroll
-      for (int g = 0; g < NGB; ++g) {
-        bh[g] = pv1[4 * g + h];
-        if (NPROD == 3) bl[g] = pv1[4 * g + 2 + h];
-      }
+      bh[g] = pv1[4 * g + h];
     }
-    const int src2 = pair_src[i2];
-    const int dst2 = pair_dst[i2];
+    if (has1 && o1 != o0) {  // uniform: the next unit has another operator
+      lds_reads_done_barrier();
+      copy_to_lds<H16>(gt + (size_t)o1 * OPU, lds4);
+      if (NPROD == 3) copy_to_lds<H16>(gt + (size_t)o1 * OPU + H16, lds4 + HPAD);
+      pending = true;
+    }
 
-    if (active) {
+    // Every wavefront stores RB * 4 times (absent columns and padding rows
+    // go to the spare row), so the wait for the copy above is exact.
+    {
       const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
       float* tile = reinterpret_cast<float*>(tiles4[wave]);
       float* part_rhs = part + (int64_t)rhs0 * n_pairs * PSTR;
+      float* spare = part + trash_row * PSTR;
       const int seg = lane & 7;
       // destination row of the columns this lane stores (c = lane/8 + 8 it)
       int64_t rowoff[4];
@@ -783,27 +813,27 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
         rowoff[it] = (int64_t)__shfl(dst0, c, 64) * PSTR;
         cok[it] = c < n0 - col0;
       }
+      const unsigned wr = lds_address(tile + r * kTilePitch + 4 * h);
+      const unsigned rd = lds_address(tile + (lane >> 3) * kTilePitch + 4 * seg);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
+        floatx4 w[4];
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4)
-          *reinterpret_cast<floatx4*>(tile + r * kTilePitch + 8 * q4 + 4 * h) =
-              floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
-                      acc[rb][4 * q4 + 3]} * sc;
-        floatx4 v[4];
-#pragma unroll
-        for (int it = 0; it < 4; ++it)
-          v[it] = *reinterpret_cast<const floatx4*>(tile + ((lane >> 3) + 8 * it) * kTilePitch +
-                                                    4 * seg);
+          w[q4] = floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                          acc[rb][4 * q4 + 3]} * sc;
+        floatx4 vv[4];
+        transpose_tile(wr, rd, w[0], w[1], w[2], w[3], vv);
         const int m = rb * 32 + 4 * seg;
 #pragma unroll
-        for (int it = 0; it < 4; ++it)
-          if (cok[it] && m + 4 <= PSTR)
-            *reinterpret_cast<floatx4*>(part_rhs + rowoff[it] + m) = v[it];
+        for (int it = 0; it < 4; ++it) {
+          float* dp = (cok[it] && m + 4 <= PSTR) ? part_rhs + rowoff[it] + m
+                                                 : spare + min(m, PSTR - 4);
+          *reinterpret_cast<floatx4*>(dp) = vv[it];
+        }
       }
     }
     o0 = o1; n0 = n1; dst0 = dst1; rhs0 = rhs1;
-    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2; rhs1 = rhs2;
     bsc0 = bsc1;
   }
 }
