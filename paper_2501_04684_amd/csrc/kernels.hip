@@ -624,7 +624,8 @@ __device__ inline void transpose_tile(unsigned waddr, unsigned raddr, floatx4 w0
 // NU rounded up to 8, zero padded), read as one 16-byte value per lane from
 // the box vector's 64-byte k-step group (the two lanes of a column read
 // adjacent 16 bytes); -Gi is a sign flip of the A values; 32-row blocks
-// cover all 2*NU rows (padding rows read row 0 and are not stored).
+// cover all 2*NU rows (padding rows read row 0; their results go to the
+// spare row).
 //
 // Per unit (a chunk, and with WALK one of its right-hand sides): pass 1 runs
 // Gh Ph and Gh Pl over all k-steps, pass 2 runs Gl Ph and, k-step by
