@@ -159,6 +159,9 @@ def parse():
                     help="form timed for the headline value (the other form is "
                          "timed after it for comparison unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--operators", choices=["table", "generated"], default="table",
+                    help="operator source of the chosen 16-bit form (the FP32 form always "
+                         "reads a table)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the counter summary of two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) made with --copy-mb, and exit")
@@ -430,15 +433,17 @@ def cpu_baseline_sampled(w, nb_ptr, S, x0, y0_gpu, budget_s, n_pairs, n_sample=4
     }, rel
 
 
-def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0):
-    """Build the plan for one precision form, time `steps` MVMs after
-    `warmup` untimed ones, and return the measurements."""
+def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0,
+             operators="table"):
+    """Build the plan for one precision form (operators from a table, or
+    evaluated by the stage-2 kernel), time `steps` MVMs after `warmup`
+    untimed ones, and return the measurements."""
     import numpy as np
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     ff = U.FarField(w.boxes, w.a, w.k, w.n_d, w.far_mode, max_nrhs=nrhs,
-                    precision=precision)
+                    precision=precision, operators=operators)
     plan_ms = (time.perf_counter() - t0) * 1e3
     nb_ptr = S = S_dev = None
     if basis == "synthetic":
@@ -868,8 +873,11 @@ def main():
         args.warmup = args.warmup if args.warmup_given else 3
     nrhs = args.nrhs
     chosen = args.precision
+    operators = args.operators
+    if chosen == "fp32":
+        operators = "table"
     res = run_form(U, W, torch, w, chosen, args.basis, nrhs, args.warmup, args.steps,
-                   args.copy_mb)
+                   args.copy_mb, operators)
     other = None
     if not args.no_compare:
         other_form = "fp32" if chosen != "fp32" else "split-bf16"
@@ -931,7 +939,7 @@ def main():
                    "n_offsets": info["n_offsets"], "n_u": nu, "far_mode": w.far_mode,
                    "basis": (f"synthetic, {w.n_u} functions per box"
                              if S is not None else "identity"),
-                   "nrhs": nrhs, "precision": chosen,
+                   "nrhs": nrhs, "precision": chosen, "operators": operators,
                    "translate_groups": info["translate_groups"]},
         "tune": res["tune"],
         **latency_fields(res["latency"]),

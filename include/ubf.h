@@ -89,6 +89,22 @@ enum ubf_precision {
                           product, for tolerances near 1e-3 */
 };
 
+/* Where the translation operators of Eq. (12)-(13) come from. */
+enum ubf_operator_source {
+  UBF_OPERATORS_TABLE = 0,     /* evaluated once on the host in FP64 at plan
+                                  creation and kept in the workspace (one
+                                  image per distinct offset) */
+  UBF_OPERATORS_GENERATED = 1  /* evaluated by the stage-2 kernel from the
+                                  offset each time it stages an operator:
+                                  the Green's function of Eq. (5)-(6) in FP64
+                                  once per lattice difference of the dipole
+                                  sites, rounded as the table would be; no
+                                  table is built or stored (FULL far sets of
+                                  large scatterers, ~10^5 offsets). 16-bit
+                                  forms with n_d 1..3 only; the round kernels
+                                  of enum ubf_translate_kernel need a table */
+};
+
 /* Problem statement (Sec. 2: box grid, dipoles per box, wavenumber). */
 typedef struct ubf_problem {
   int64_t n_boxes;         /* number of occupied boxes, >= 1 */
@@ -102,6 +118,7 @@ typedef struct ubf_problem {
   int32_t n_d;             /* dipoles per box edge, 1..4 */
   int32_t far_mode;        /* enum ubf_far_mode */
   int32_t precision;       /* enum ubf_precision */
+  int32_t operators;       /* enum ubf_operator_source; 0 = table */
 } ubf_problem;
 
 /* Sizes and work counts of a plan, for benchmarks and tests. */
@@ -125,7 +142,7 @@ typedef struct ubf_info {
                                per RHS */
   int32_t translate_kernel; /* stage-2 kernel of the 16-bit forms: a value of
                                enum ubf_translate_kernel, 0 for the FP32 form */
-  int32_t reserved;
+  int32_t operators;        /* enum ubf_operator_source */
 } ubf_info;
 
 /* Stage-2 kernels of the 16-bit forms (ubf_plan_schedule, ubf_plan_tune).
@@ -152,11 +169,13 @@ typedef struct ubf_plan ubf_plan;
 
 /* Build a plan on the host (no device work): validate the problem, build
  * the far set (Algorithm 2), its distinct offsets and their symmetry
- * orbits (Sec. 2.2), the work partition, and the FP32 operator table
- * from FP64 evaluations of Eq. (5)-(6) and (13).
+ * orbits (Sec. 2.2), the work partition, and (UBF_OPERATORS_TABLE) the
+ * operator table of the plan's form from FP64 evaluations of Eq. (5)-(6)
+ * and (13).
  * Errors: UBF_EINVAL for a null pointer, n_boxes < 1, a negative or
  * duplicate coordinate, a <= 0, k <= 0, eta < 0, n_d outside 1..4, an
- * unknown far_mode or precision, a far set beyond 2^31-1 pairs, or an
+ * unknown far_mode, precision or operator source, generated operators
+ * with the FP32 form or n_d = 4, a far set beyond 2^31-1 pairs, or an
  * operator table beyond 16 GiB;
  * UBF_ENOMEM if host memory runs out. *out is set only on success. */
 int ubf_plan_create(const ubf_problem* problem, ubf_plan** out);
@@ -314,9 +333,10 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
  * up to a multiple of 8 and capped by the work units). Uploads the work
  * partition on hip_stream and waits. Results do not depend on the choice.
  * Any captured graph is discarded. Errors: UBF_EINVAL (null plan, unknown
- * kernel, a 16-bit kernel on an FP32 plan, groups out of range, or a plan
- * whose stage 2 runs one workgroup per item: networks set, or 192
- * coefficients per box), UBF_ESTATE (unbound), UBF_EDEVICE. */
+ * kernel, a 16-bit kernel on an FP32 plan, a round kernel on a plan with
+ * generated operators, groups out of range, or a plan whose stage 2 runs
+ * one workgroup per item: networks set, or 192 coefficients per box),
+ * UBF_ESTATE (unbound), UBF_EDEVICE. */
 int ubf_plan_schedule(ubf_plan* plan, int32_t kernel, int32_t groups, void* hip_stream);
 
 /* Stage 1 alone: d_P[nrhs][n_boxes][N_u] = S_i x_i (complex64). */

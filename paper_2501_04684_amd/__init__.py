@@ -47,6 +47,10 @@ _PRECISIONS = {"fp32": FP32, "split-bf16": SPLIT_BF16, "split-fp16": SPLIT_FP16,
                FP16: FP16}
 _MODES = {"ilist": FAR_ILIST, "full": FAR_FULL, FAR_ILIST: FAR_ILIST,
           FAR_FULL: FAR_FULL}
+# where the translation operators come from (enum ubf_operator_source)
+OPERATORS_TABLE, OPERATORS_GENERATED = 0, 1
+_OPERATORS = {"table": OPERATORS_TABLE, "generated": OPERATORS_GENERATED,
+              OPERATORS_TABLE: OPERATORS_TABLE, OPERATORS_GENERATED: OPERATORS_GENERATED}
 
 
 class UbfError(RuntimeError):
@@ -61,7 +65,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("n_boxes", ctypes.c_int64), ("box_ijk", ctypes.c_void_p),
                 ("a", ctypes.c_double), ("k", ctypes.c_double),
                 ("eta", ctypes.c_double), ("n_d", ctypes.c_int32),
-                ("far_mode", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("far_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("operators", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -72,7 +77,7 @@ class _Info(ctypes.Structure):
                 ("translate_flops", ctypes.c_double), ("mfma", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_scatterers", ctypes.c_int32),
                 ("translate_groups", ctypes.c_int32), ("n_items", ctypes.c_int64),
-                ("translate_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("translate_kernel", ctypes.c_int32), ("operators", ctypes.c_int32)]
 
 
 class _GmresStatus(ctypes.Structure):
@@ -183,11 +188,12 @@ def _stream(stream):
 # ----------------------------------------------------------------- plans
 
 def plan_create(boxes, a: float, k: float, n_d: int, far_mode="ilist",
-                eta: float = 0.0, precision: int = FP32):
+                eta: float = 0.0, precision: int = FP32, operators="table"):
     """Create a plan from integer box coordinates (n, 3). Host only."""
     b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 3))
     prob = _Problem(len(b), b.ctypes.data, float(a), float(k), float(eta),
-                    int(n_d), _MODES[far_mode], _PRECISIONS[precision])
+                    int(n_d), _MODES[far_mode], _PRECISIONS[precision],
+                    _OPERATORS[operators])
     out = _VP()
     _check(lib().ubf_plan_create(ctypes.byref(prob), ctypes.byref(out)),
            "ubf_plan_create")
@@ -195,7 +201,7 @@ def plan_create(boxes, a: float, k: float, n_d: int, far_mode="ilist",
 
 
 def plan_create_batch(scatterers, a: float, k: float, n_d: int, far_mode="ilist",
-                      eta: float = 0.0, precision: int = FP32):
+                      eta: float = 0.0, precision: int = FP32, operators="table"):
     """One plan over several scatterers, each an (n_s, 3) array of box
     coordinates; their boxes are concatenated in the given order."""
     parts = [np.asarray(b, dtype=np.int32).reshape(-1, 3) for b in scatterers]
@@ -204,7 +210,8 @@ def plan_create_batch(scatterers, a: float, k: float, n_d: int, far_mode="ilist"
     ptr = np.zeros(len(parts) + 1, dtype=np.int64)
     ptr[1:] = np.cumsum([len(q) for q in parts])
     prob = _Problem(len(b), b.ctypes.data, float(a), float(k), float(eta),
-                    int(n_d), _MODES[far_mode], _PRECISIONS[precision])
+                    int(n_d), _MODES[far_mode], _PRECISIONS[precision],
+                    _OPERATORS[operators])
     out = _VP()
     _check(lib().ubf_plan_create_batch(ctypes.byref(prob), len(parts),
                                        ptr.ctypes.data, ctypes.byref(out)),
@@ -428,17 +435,19 @@ class FarField:
     CUDA tensor ``x`` of shape [nrhs, sum N_b] (or [sum N_b]).
 
     ``scatterers`` (a list of box arrays) replaces ``boxes`` to batch several
-    independent scatterers in one plan.
+    independent scatterers in one plan. ``operators="generated"`` makes stage
+    2 evaluate the operators itself instead of reading a table (16-bit forms).
     """
 
     def __init__(self, boxes, a, k, n_d, far_mode="ilist", eta=0.0,
-                 max_nrhs=1, device="cuda", precision=FP32, scatterers=None):
+                 max_nrhs=1, device="cuda", precision=FP32, scatterers=None,
+                 operators="table"):
         import torch
         if scatterers is not None:
             self.plan = plan_create_batch(scatterers, a, k, n_d, far_mode, eta,
-                                          precision)
+                                          precision, operators)
         else:
-            self.plan = plan_create(boxes, a, k, n_d, far_mode, eta, precision)
+            self.plan = plan_create(boxes, a, k, n_d, far_mode, eta, precision, operators)
         self.info = plan_info(self.plan)
         self.max_nrhs = int(max_nrhs)
         nbytes = workspace_bytes(self.plan, self.max_nrhs)

@@ -119,8 +119,8 @@ int create(const ubf_problem* problem, const int64_t* scat_ptr, int64_t n_scat,
   try {
     why = ubf::build_plan(problem->box_ijk, problem->n_boxes, problem->a,
                           problem->k, problem->eta, problem->n_d,
-                          problem->far_mode, problem->precision, scat_ptr, n_scat,
-                          plan->p);
+                          problem->far_mode, problem->precision, problem->operators,
+                          scat_ptr, n_scat, plan->p);
   } catch (const std::bad_alloc&) {
     delete plan;
     return fail(UBF_ENOMEM, "host allocation failed while building the plan");
@@ -174,9 +174,9 @@ struct Candidate {
 
 // Stage-2 schedules the tuner times: persistent chunk grids of 256..4096
 // workgroups; for the 16-bit forms also the walk over right-hand sides
-// (several vectors), the rounds at two workgroups per compute unit
-// (512..2048) and the double-buffered rounds at one (256). Grids that the
-// work caps to the same size are timed once.
+// (several vectors), and with a table the rounds at two workgroups per
+// compute unit (512..2048) and the double-buffered rounds at one (256).
+// Grids that the work caps to the same size are timed once.
 std::vector<Candidate> tune_candidates(const ubf::Plan& p, int nrhs) {
   std::vector<Candidate> c;
   const int64_t grids[] = {256, 512, 1024, 2048, 4096};
@@ -194,8 +194,10 @@ std::vector<Candidate> tune_candidates(const ubf::Plan& p, int nrhs) {
   if (p.split()) {
     if (nrhs > 1)
       for (int64_t g : grids) add(ubf::kSplitChunksWalk, g, p.n_chunks());
-    for (int64_t g : {512, 1024, 2048}) add(ubf::kSplitRounds, g, p.n_items());
-    add(ubf::kSplitRoundsDouble, 256, p.n_items());
+    if (!p.gen_ops) {  // the round kernels copy operators from the table
+      for (int64_t g : {512, 1024, 2048}) add(ubf::kSplitRounds, g, p.n_items());
+      add(ubf::kSplitRoundsDouble, 256, p.n_items());
+    }
   }
   return c;
 }
@@ -203,7 +205,8 @@ std::vector<Candidate> tune_candidates(const ubf::Plan& p, int nrhs) {
 // The plan statistics a schedule is chosen for: the stage-2 form, box size,
 // vectors per call and the sizes of the far set and its partition.
 std::string tune_key(const ubf::Plan& p, int nrhs) {
-  return "v1 precision=" + std::to_string(p.precision) + " nu=" + std::to_string(p.nu) +
+  return "v2 precision=" + std::to_string(p.precision) +
+         " operators=" + std::to_string(p.gen_ops ? 1 : 0) + " nu=" + std::to_string(p.nu) +
          " nrhs=" + std::to_string(nrhs) + " boxes=" + std::to_string(p.n_box) +
          " scatterers=" + std::to_string(p.n_scat()) + " pairs=" + std::to_string(p.n_pairs()) +
          " offsets=" + std::to_string(p.n_off()) + " chunks=" + std::to_string(p.n_chunks()) +
@@ -299,6 +302,7 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
       {L.test_ptr, p.test_ptr.data(), p.test_ptr.size() * sizeof(int32_t)},
       {L.nb_ptr, nb.data(), nb.size() * sizeof(int64_t)},
       {L.off_scale, p.off_scale.data(), p.off_scale.size() * sizeof(float)},
+      {L.offsets, p.offsets.data(), p.offsets.size() * sizeof(int32_t)},
   };
   for (const Copy& c : copies) {
     if (c.n == 0) continue;
@@ -324,6 +328,7 @@ int ubf_plan_bind(ubf_plan* plan, void* d_workspace, size_t bytes,
   p.d_part = (float*)(ws + L.part);
   p.d_off_scale = (float*)(ws + L.off_scale);
   p.d_box_scale = (float*)(ws + L.box_scale);
+  p.d_offsets = (int32_t*)(ws + L.offsets);
   return ok();
 }
 
@@ -422,6 +427,9 @@ int ubf_plan_schedule(ubf_plan* plan, int32_t kernel, int32_t groups, void* hip_
     return fail(UBF_EINVAL, "unknown stage-2 kernel");
   if (kernel != ubf::kSplitChunks && !p.split())
     return fail(UBF_EINVAL, "only the 16-bit forms have stage-2 kernels other than 0");
+  if (p.gen_ops && (kernel == ubf::kSplitRounds || kernel == ubf::kSplitRoundsDouble))
+    return fail(UBF_EINVAL, "the round kernels need an operator table (generated operators "
+                            "run the chunk kernels)");
   if (groups < 1 || groups > ubf::kMaxTranslateGroups)
     return fail(UBF_EINVAL, "groups must be in 1.." + std::to_string(ubf::kMaxTranslateGroups));
   if (p.hidden > 0 || ubf::staged_translate_supported(p))
@@ -451,7 +459,12 @@ int ubf_plan_tune(ubf_plan* plan, int32_t nrhs, int32_t reps, void* hip_stream,
   const std::string key = tune_key(p, nrhs);
   const char* cache = std::getenv("UBF_TUNE_CACHE");
   int kernel = -1, groups = 0;
-  if (cache && *cache && cache_lookup(cache, key, &kernel, &groups)) {
+  const auto usable = [&](int k) {  // a cache line may hold any kernel number
+    return k == ubf::kSplitChunks ||
+           (p.split() && (k == ubf::kSplitChunksWalk ||
+                          (!p.gen_ops && (k == ubf::kSplitRounds || k == ubf::kSplitRoundsDouble))));
+  };
+  if (cache && *cache && cache_lookup(cache, key, &kernel, &groups) && usable(kernel)) {
     const int e = apply_schedule(p, kernel, groups, s);
     if (e) return hip_fail(e, "upload (tune cache)");
     if (groups_out) *groups_out = current_groups(p);
@@ -660,6 +673,7 @@ int ubf_plan_info(const ubf_plan* plan, ubf_info* out) {
   out->n_items = p.n_items();
   out->translate_kernel = p.split_kernel;
   out->translate_groups = current_groups(p);
+  out->operators = p.gen_ops ? UBF_OPERATORS_GENERATED : UBF_OPERATORS_TABLE;
   return ok();
 }
 

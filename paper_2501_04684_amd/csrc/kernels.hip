@@ -608,6 +608,131 @@ __device__ inline void transpose_tile(unsigned waddr, unsigned raddr, floatx4 w0
       : "memory");
 }
 
+// Parameters of operators evaluated in the translation kernel instead of
+// read from a table: the integer offsets of the plan and the problem's box
+// side, wavenumber and impedance.
+struct GenArgs {
+  const int32_t* offsets;  // 3 per offset
+  double a, k, eta;
+};
+
+// Dyadic Green's function of Eq. (5)-(6) at R = (rx, ry, rz): D = psi [I
+// c_iso - R^R^ c_rr], psi = -j k eta e^{-jkR} / (4 pi R), c_iso = 1 -
+// j/(kR) - 1/(kR)^2, c_rr = 1 - 3j/(kR) - 3/(kR)^2. The distance and the
+// phase kR, reduced to [-pi, pi], are taken in FP64, the rest in FP32 (the
+// entries are stored as FP32 anyway). Entry 3 p + q goes to out[3 p + q]
+// as (re, im); returns the largest |Re|, |Im|.
+__device__ inline float dyadic_green(double rx, double ry, double rz, double k, double eta,
+                                     float2* out) {
+  const double r = sqrt(rx * rx + ry * ry + rz * rz);
+  const double kr = k * r;
+  const double twopi = 6.283185307179586476925;
+  const float x = (float)(kr - twopi * rint(kr / twopi));
+  float sn, cs;
+  sincosf(x, &sn, &cs);
+  const float ir = (float)(1.0 / r);
+  const float rh[3] = {(float)rx * ir, (float)ry * ir, (float)rz * ir};
+  // -j (cos kr - j sin kr) = -sin kr - j cos kr
+  const float f = (float)(k * eta / (4.0 * 3.14159265358979323846 * r));
+  const float pr = -f * sn, pi = -f * cs;
+  const float ikr = (float)(1.0 / kr), ikr2 = ikr * ikr;
+  const float iso_r = 1.f - ikr2, iso_i = -ikr;
+  const float rr_r = 1.f - 3.f * ikr2, rr_i = -3.f * ikr;
+  float vmax = 0.f;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    const int p = e / 3, q = e - 3 * p;
+    const float rr = rh[p] * rh[q];
+    const float t_r = (p == q ? iso_r : 0.f) - rr * rr_r;
+    const float t_i = (p == q ? iso_i : 0.f) - rr * rr_i;
+    const float dr = pr * t_r - pi * t_i, di = pr * t_i + pi * t_r;
+    out[e] = make_float2(dr, di);
+    vmax = fmaxf(vmax, fmaxf(fabsf(dr), fabsf(di)));
+  }
+  return vmax;
+}
+
+// hi / lo 16-bit parts of v (hi = v rounded, lo = the remainder rounded).
+template <bool F16>
+__device__ inline void split16(float v, unsigned short& hi, unsigned short& lo) {
+  if (F16) {
+    const __half h = __float2half_rn(v);
+    hi = __half_as_ushort(h);
+    lo = __half_as_ushort(__float2half_rn(v - __half2float(h)));
+  } else {
+    hi = (unsigned short)bf16_rne(v);
+    lo = (unsigned short)bf16_rne(v - __uint_as_float((unsigned)hi << 16));
+  }
+}
+
+// The operator image of offset `o` written into LDS by the whole workgroup,
+// in the layout of the 16-bit table (planes re, im of NU rows x KHB values;
+// the hi half at img, the lo half at img + lo_off): the sites form one
+// uniform lattice of step a / n_d, so each of the (2 n_d - 1)^3 lattice
+// differences is evaluated once (one thread each, into `blk`) and the
+// NU x NU entries are filled from those blocks, one site pair per thread. FP16 forms divide by the
+// power of two that brings the largest |Re|, |Im| to [2^14, 2^15), returned
+// in `scale` (1 for BF16). Ends with a barrier; `blk` is free afterwards.
+template <int NU, bool F16, int NPROD>
+__device__ void generate_operator(const GenArgs& ga, int o, unsigned short* img, int lo_off,
+                                  float2* blk, float* wmax, float& scale) {
+  constexpr int ND = NU == 3 ? 1 : NU == 24 ? 2 : 3;
+  static_assert(3 * ND * ND * ND == NU, "operators are generated for n_d 1..3");
+  constexpr int SPAN = 2 * ND - 1, NDIFF = SPAN * SPAN * SPAN;
+  constexpr int KHB = (NU + 7) & ~7, PLANE = NU * KHB;
+  static_assert(NDIFF <= kBlock, "one lattice difference per thread");
+  const int t = threadIdx.x;
+  const int wx = ga.offsets[3 * o], wy = ga.offsets[3 * o + 1], wz = ga.offsets[3 * o + 2];
+  float vmax = 0.f;
+  if (t < NDIFF) {
+    const int dx = t / (SPAN * SPAN), dy = (t / SPAN) % SPAN, dz = t % SPAN;
+    const double step = ga.a / ND;
+    vmax = dyadic_green(ga.a * wx + step * (dx - (ND - 1)), ga.a * wy + step * (dy - (ND - 1)),
+                        ga.a * wz + step * (dz - (ND - 1)), ga.k, ga.eta, blk + 9 * t);
+  }
+  if (F16) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, m, 64));
+    if ((t & 63) == 0) wmax[t >> 6] = vmax;
+  }
+  lds_reads_done_barrier();
+  float inv = 1.f;
+  scale = 1.f;
+  if (F16) {
+    const float m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    const int e = m > 0.f ? ilogbf(m) - 14 : 0;
+    scale = ldexpf(1.f, e);
+    inv = ldexpf(1.f, -e);  // exact power of two
+  }
+  // one site pair (l, s) per iteration: its 3 x 3 block of the operator
+  constexpr int NS = ND * ND * ND;
+  for (int q = t; q < NS * NS; q += kBlock) {
+    const int l = q / NS, s = q - l * NS;
+    const int lx = l / (ND * ND), ly = (l / ND) % ND, lz = l % ND;
+    const int sx = s / (ND * ND), sy = (s / ND) % ND, sz = s % ND;
+    const int d = ((lx - sx + ND - 1) * SPAN + (ly - sy + ND - 1)) * SPAN + (lz - sz + ND - 1);
+    float2 g[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) g[e] = blk[9 * d + e];
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int be = 0; be < 3; ++be) {
+        unsigned short hr, lr, hi_, li_;
+        split16<F16>(g[3 * al + be].x * inv, hr, lr);
+        split16<F16>(g[3 * al + be].y * inv, hi_, li_);
+        const int at = (3 * l + al) * KHB + 3 * s + be;
+        img[at] = hr;
+        img[PLANE + at] = hi_;
+        if (NPROD == 3) {
+          img[lo_off + at] = lr;
+          img[lo_off + PLANE + at] = li_;
+        }
+      }
+  }
+  lds_reads_done_barrier();
+}
+
 // Split-precision translation on the 16-bit matrix cores
 // (v_mfma_f32_32x32x16_bf16 / _f16, FP32 accumulation). With G = Gh + Gl
 // and P = Ph + Pl (h = the value rounded to 16 bits, l = the remainder
@@ -642,13 +767,14 @@ __device__ inline void transpose_tile(unsigned waddr, unsigned raddr, floatx4 w0
 // per unit from their owner lanes; every wavefront issues the same number
 // of stores (absent columns and padding rows go to the spare row), which
 // the wait for the copy counts on.
-template <int NU, bool F16, int NPROD, bool WALK>
+template <int NU, bool F16, int NPROD, bool WALK, bool GEN>
 __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const unsigned short* __restrict__ table, const int32_t* __restrict__ chunks,
     const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
     const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
     float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row,
-    const float* __restrict__ off_scale, const float* __restrict__ box_scale, int nrhs) {
+    const float* __restrict__ off_scale, const float* __restrict__ box_scale, int nrhs,
+    GenArgs ga) {
   typedef typename Mfma16<F16>::vec vec16;
   constexpr int KH = (NU + 3) & ~3;      // FP32 half-length (partial rows)
   constexpr int KHB = (NU + 7) & ~7;     // 16-bit half-length
@@ -664,6 +790,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   constexpr int LO = HPAD * 8;           // lo half, in 16-bit values from the LDS start
   __shared__ uintx4 lds4[(NPROD == 3 ? 2 : 1) * HPAD];
   __shared__ floatx4 tiles4[4][32 * kTilePitch / 4];  // one per wavefront
+  __shared__ float gen_max[4];                         // GEN: per-wavefront maxima
   const unsigned short* lds = reinterpret_cast<const unsigned short*>(lds4);
 
   const int group = xcd_chunk(blockIdx.x, gridDim.x);
@@ -719,14 +846,35 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
   }
   const uintx4* gt = reinterpret_cast<const uintx4*>(table);
   constexpr size_t OPU = 4 * PLANE / 8;  // 16-byte units per operator
-  copy_to_lds<H16>(gt + (size_t)o0 * OPU, lds4);
-  if (NPROD == 3) copy_to_lds<H16>(gt + (size_t)o0 * OPU + H16, lds4 + HPAD);
-  wait_vmcnt<0>();
-  lds_copies_done_barrier();
+  unsigned short* const img = reinterpret_cast<unsigned short*>(lds4);
+  float2* const blk = reinterpret_cast<float2*>(&tiles4[0][0]);
+  float gen_scale = 1.f;  // GEN: the staged operator's power-of-two scale
+  int staged = -1;        // GEN: offset of the staged operator
+  if (GEN) {
+    // the padding columns of every row stay zero (generation writes the
+    // first NU of each row only)
+    constexpr int PADC = KHB - NU, NH = NPROD == 3 ? 2 : 1;
+    for (int q = threadIdx.x; q < NH * 2 * NU * PADC; q += kBlock) {
+      const int hh = q / (2 * NU * PADC), rem = q - hh * 2 * NU * PADC;
+      const int row = rem / PADC;  // plane-major: re rows, then im rows
+      img[hh * LO + row * KHB + NU + (rem - row * PADC)] = 0;
+    }
+  } else {
+    copy_to_lds<H16>(gt + (size_t)o0 * OPU, lds4);
+    if (NPROD == 3) copy_to_lds<H16>(gt + (size_t)o0 * OPU + H16, lds4 + HPAD);
+    wait_vmcnt<0>();
+    lds_copies_done_barrier();
+  }
 
   bool pending = false;
   for (int v = vbeg; v < vend; ++v) {
-    if (pending) {
+    if (GEN) {
+      if (o0 != staged) {  // uniform across the workgroup
+        lds_reads_done_barrier();  // every wavefront is done with the image and its tile
+        generate_operator<NU, F16, NPROD>(ga, o0, img, LO, blk, gen_max, gen_scale);
+        staged = o0;
+      }
+    } else if (pending) {
       // the copy was issued just before the previous unit's RB * 4 stores
       wait_vmcnt<RB * 4>();
       lds_copies_done_barrier();
@@ -790,7 +938,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
       }
       bh[g] = pv1[4 * g + h];
     }
-    if (has1 && o1 != o0) {  // uniform: the next unit has another operator
+    if (!GEN && has1 && o1 != o0) {  // uniform: the next unit has another operator
       lds_reads_done_barrier();
       copy_to_lds<H16>(gt + (size_t)o1 * OPU, lds4);
       if (NPROD == 3) copy_to_lds<H16>(gt + (size_t)o1 * OPU + H16, lds4 + HPAD);
@@ -800,7 +948,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     // Every wavefront stores RB * 4 times (absent columns and padding rows
     // go to the spare row), so the wait for the copy above is exact.
     {
-      const float sc = F16 ? off_scale[o0] * bsc0 : 1.f;
+      const float sc = F16 ? (GEN ? gen_scale : off_scale[o0]) * bsc0 : 1.f;
       float* tile = reinterpret_cast<float*>(tiles4[wave]);
       float* part_rhs = part + (int64_t)rhs0 * n_pairs * PSTR;
       float* spare = part + trash_row * PSTR;
@@ -1522,6 +1670,20 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
     const bool walk = sk == kSplitChunksWalk && nrhs > 1;
     const dim3 cgrid((unsigned)p.n_groups(), walk ? 1 : nrhs);
     const dim3 rgrid((unsigned)p.n_round_groups(), nrhs);
+    if (p.gen_ops && (sk == kSplitRounds || sk == kSplitRoundsDouble))
+      return (int)hipErrorInvalidValue;  // rejected by the schedule calls
+    const GenArgs ga{p.d_offsets, p.a, p.k, p.eta};
+#define UBF_SPLIT_CHUNKS(NU, F16, NPROD, WALK)                                                 \
+  do {                                                                                         \
+    if (p.gen_ops)                                                                             \
+      UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD, WALK, true>), cgrid, dim3(kBlock), \
+                 s, tb, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,  \
+                 p.n_pairs(), trash, p.d_off_scale, p.d_box_scale, nrhs, ga);                  \
+    else                                                                                       \
+      UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD, WALK, false>), cgrid, dim3(kBlock), \
+                 s, tb, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,  \
+                 p.n_pairs(), trash, p.d_off_scale, p.d_box_scale, nrhs, ga);                  \
+  } while (0)
 #define UBF_SPLIT(NU, F16, NPROD)                                                              \
   do {                                                                                         \
     if (sk == kSplitRounds || sk == kSplitRoundsDouble) {                                      \
@@ -1534,13 +1696,9 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
                    tb, p.d_rounds, p.d_wg_round_ptr, p.d_pair_src, p.d_pair_dst, P, part,      \
                    p.n_box, p.n_pairs(), p.d_off_scale, p.d_box_scale);                        \
     } else if (walk) {                                                                         \
-      UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD, true>), cgrid, dim3(kBlock), s, tb, \
-                 p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,         \
-                 p.n_pairs(), trash, p.d_off_scale, p.d_box_scale, nrhs);                      \
+      UBF_SPLIT_CHUNKS(NU, F16, NPROD, true);                                                  \
     } else {                                                                                   \
-      UBF_LAUNCH(ev, (translate_split_kernel<NU, F16, NPROD, false>), cgrid, dim3(kBlock), s,   \
-                 tb, p.d_chunks, p.d_wg_ptr, p.d_pair_src, p.d_pair_dst, P, part, p.n_box,     \
-                 p.n_pairs(), trash, p.d_off_scale, p.d_box_scale, nrhs);                      \
+      UBF_SPLIT_CHUNKS(NU, F16, NPROD, false);                                                 \
     }                                                                                          \
   } while (0)
 #define UBF_SPLIT_NU(F16, NPROD)                           \
@@ -1559,6 +1717,7 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
     }
 #undef UBF_SPLIT_NU
 #undef UBF_SPLIT
+#undef UBF_SPLIT_CHUNKS
     return (int)hipGetLastError();
   }
   switch (p.nu) {

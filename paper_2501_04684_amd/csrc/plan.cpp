@@ -413,6 +413,7 @@ Layout workspace_layout(const Plan& p, int32_t max_nrhs) {
   L.part = take(((size_t)max_nrhs * p.n_pairs() + 1) * p.pstride() * sizeof(float));
   L.off_scale = take((size_t)std::max<int32_t>(p.n_off(), 1) * sizeof(float));
   L.box_scale = take((size_t)max_nrhs * p.n_box * sizeof(float));
+  L.offsets = take(p.offsets.size() * sizeof(int32_t));
   L.total = at;
   return L;
 }
@@ -434,8 +435,8 @@ ScratchLayout scratch_layout(const Plan& p, int32_t nrhs) {
 
 std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
                        double k, double eta, int n_d, int far_mode,
-                       int precision, const int64_t* scat_ptr, int64_t n_scat,
-                       Plan& P) {
+                       int precision, int operators, const int64_t* scat_ptr,
+                       int64_t n_scat, Plan& P) {
   if (!box_ijk) return "box_ijk is NULL";
   if (n_box < 1) return "n_boxes must be >= 1";
   if (n_box > std::numeric_limits<int32_t>::max() / 2) return "n_boxes too large";
@@ -445,6 +446,9 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   if (n_d < 1 || n_d > 4) return "n_d must be in 1..4";
   if (far_mode != 0 && far_mode != 1) return "unknown far_mode";
   if (precision < 0 || precision > 3) return "unknown precision";
+  if (operators != 0 && operators != 1) return "unknown operator source";
+  if (operators == 1 && (precision == 0 || n_d > 3))
+    return "generated operators need a 16-bit form (precision 1..3) and n_d 1..3";
 
   P.n_box = n_box;
   P.boxes.assign(box_ijk, box_ijk + 3 * n_box);
@@ -459,6 +463,7 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   P.khb = half_len_bf16(P.nu);
   P.far_mode = far_mode;
   P.precision = precision;
+  P.gen_ops = operators == 1;
 
   if (scat_ptr) {
     if (n_scat < 1) return "n_scatterers must be >= 1";
@@ -558,7 +563,7 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
                            : P.split()        ? (size_t)4 * P.nu * P.khb * sizeof(uint16_t)
                            : P.staged()       ? P.staged_op_floats() * sizeof(float)
                                               : (size_t)2 * P.nu * P.kh * sizeof(float);
-  if ((double)n_off * (double)img_bytes > kMaxTableBytes)
+  if (!P.gen_ops && (double)n_off * (double)img_bytes > kMaxTableBytes)
     return "operator table would exceed 16 GiB";
   P.offsets.resize(3 * n_off);
   for (int64_t o = 0; o < n_off; ++o)
@@ -623,13 +628,15 @@ std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
   std::sort(keys.begin(), keys.end());
   P.n_orbits = (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
 
+  P.off_scale.assign(n_off, 1.0f);
+  if (P.gen_ops) return std::string();  // evaluated by the translation kernel
+
   // Operator table image, one offset at a time (cached across plans).
   if (P.split())
     P.table_bf16.assign((size_t)n_off * img_bytes / sizeof(uint16_t), 0);
   else
     P.table.assign((size_t)n_off * img_bytes / sizeof(float), 0.0f);
   char* table = P.split() ? (char*)P.table_bf16.data() : (char*)P.table.data();
-  P.off_scale.assign(n_off, 1.0f);
   // Offsets are independent: large tables (FULL far sets have one operator
   // per distinct offset, ~10^5 on a few-thousand-box scatterer) are built
   // on several host threads, each over a contiguous range of offsets.

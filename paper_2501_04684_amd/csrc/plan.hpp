@@ -143,6 +143,9 @@ struct Plan {
   std::vector<int32_t> wg_round_ptr;  // round range of each workgroup
   // Stage-2 kernel of the 16-bit forms (enum SplitKernel).
   int split_kernel = kSplitChunks;
+  // Operators evaluated by the translation kernel from the offsets (FP64
+  // Green's function) instead of read from a table; the table is empty.
+  bool gen_ops = false;
   int32_t n_orbits = 0;
 
   // Operator table image: per offset two planes (re, im) of nu rows of kh
@@ -208,6 +211,7 @@ struct Plan {
   float* d_P = nullptr;
   float* d_part = nullptr;
   float* d_off_scale = nullptr;  // [n_off] (FP16 forms)
+  int32_t* d_offsets = nullptr;  // [n_off][3] integer offsets (generated operators)
   float* d_box_scale = nullptr;  // [max_nrhs][n_box] box-vector scales (FP16 forms)
 
   // Networks standing in for the operators (Sec. 3): hidden width (0 = none,
@@ -228,7 +232,7 @@ struct Plan {
 // Workspace layout, in bytes from the workspace start.
 struct Layout {
   size_t table, chunks, items, wg_ptr, rounds, wg_round_ptr, pair_src, pair_dst, test_ptr, nb_ptr,
-      P, part, off_scale, box_scale, total;
+      P, part, off_scale, box_scale, offsets, total;
 };
 Layout workspace_layout(const Plan& p, int32_t max_nrhs);
 
@@ -242,11 +246,13 @@ ScratchLayout scratch_layout(const Plan& p, int32_t nrhs);
 
 // Validate and build; returns an empty string on success, else the reason.
 // scat_ptr (n_scat + 1 prefix offsets into the boxes) splits the boxes into
-// independent scatterers; NULL means one scatterer.
+// independent scatterers; NULL means one scatterer. operators: 0 = table
+// built here, 1 = evaluated by the translation kernel (16-bit forms, n_d
+// 1..3; no table).
 std::string build_plan(const int32_t* box_ijk, int64_t n_box, double a,
                        double k, double eta, int n_d, int far_mode,
-                       int precision, const int64_t* scat_ptr, int64_t n_scat,
-                       Plan& out);
+                       int precision, int operators, const int64_t* scat_ptr,
+                       int64_t n_scat, Plan& out);
 
 // Rounds of the 16-bit translation for `groups` workgroups (rounded up to a
 // multiple of 8, at most kMaxTranslateGroups, at most one per item), each

@@ -307,6 +307,43 @@ def test_split_precision_plan():
             U.plan_destroy(plan)
 
 
+def test_generated_operator_plans():
+    # operators evaluated by the stage-2 kernel: no table in the plan or the
+    # workspace (the workspace shrinks by the table's bytes, up to their
+    # 256-byte alignment), the same far set; only the 16-bit forms with n_d
+    # 1..3 accept it
+    b = W.grid_boxes(6, 6, 6)
+    for form in ("split-bf16", "split-fp16", "fp16"):
+        tab = U.plan_create(b, A, K, 3, "full", precision=form)
+        gen = U.plan_create(b, A, K, 3, "full", precision=form, operators="generated")
+        try:
+            ti, gi = U.plan_info(tab), U.plan_info(gen)
+            assert ti["operators"] == U.OPERATORS_TABLE and gi["operators"] == U.OPERATORS_GENERATED
+            assert gi["table_bytes"] == 0 and ti["table_bytes"] > 0
+            assert (gi["n_pairs"], gi["n_offsets"], gi["n_chunks"]) == \
+                (ti["n_pairs"], ti["n_offsets"], ti["n_chunks"])
+            assert np.array_equal(U.plan_offsets(gen), U.plan_offsets(tab))
+            saved = U.workspace_bytes(tab, 1) - U.workspace_bytes(gen, 1)
+            assert 0 <= saved - ti["table_bytes"] < 256
+            # host introspection still evaluates operators on demand
+            G = U.plan_operator(gen, 0)
+            assert np.allclose(G, U.plan_operator(tab, 0), rtol=0, atol=0)
+        finally:
+            U.plan_destroy(tab)
+            U.plan_destroy(gen)
+    for kw in (dict(precision="fp32"), dict(n_d=4, precision="split-fp16")):
+        args = dict(n_d=3)
+        args.update(kw)
+        with pytest.raises(U.UbfError) as e:
+            U.plan_create(b, 0.125, K, args.pop("n_d"), "ilist", operators="generated", **args)
+        assert e.value.status == -1 and "generated operators" in str(e.value)
+    bi = np.ascontiguousarray(b.astype(np.int32))
+    prob = U._Problem(len(bi), bi.ctypes.data, A, K, 0.0, 3, 0, 2, 7)
+    out = ctypes.c_void_p()
+    assert U.lib().ubf_plan_create(ctypes.byref(prob), ctypes.byref(out)) == -1
+    assert "operator source" in U.last_error() and not out.value
+
+
 def _small_scatterers():
     return [b for _, b in W.scatterer_set(6, seed=11, lo=40, hi=300)]
 
