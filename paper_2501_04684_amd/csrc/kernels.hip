@@ -613,7 +613,9 @@ __device__ inline void transpose_tile(unsigned waddr, unsigned raddr, floatx4 w0
 // side, wavenumber and impedance.
 struct GenArgs {
   const int32_t* offsets;  // 3 per offset
-  double a, k, eta;
+  double a, k;
+  float inv_k;  // 1 / k
+  float psi0;   // k eta / (4 pi): |psi| R
 };
 
 // Dyadic Green's function of Eq. (5)-(6) at R = (rx, ry, rz): D = psi [I
@@ -622,20 +624,20 @@ struct GenArgs {
 // phase kR, reduced to [-pi, pi], are taken in FP64, the rest in FP32 (the
 // entries are stored as FP32 anyway). Entry 3 p + q goes to out[3 p + q]
 // as (re, im); returns the largest |Re|, |Im|.
-__device__ inline float dyadic_green(double rx, double ry, double rz, double k, double eta,
+__device__ inline float dyadic_green(double rx, double ry, double rz, const GenArgs& ga,
                                      float2* out) {
   const double r = sqrt(rx * rx + ry * ry + rz * rz);
-  const double kr = k * r;
+  const double kr = ga.k * r;
   const double twopi = 6.283185307179586476925;
-  const float x = (float)(kr - twopi * rint(kr / twopi));
+  const float x = (float)(kr - twopi * rint(kr * (1.0 / twopi)));
   float sn, cs;
   sincosf(x, &sn, &cs);
   const float ir = (float)(1.0 / r);
   const float rh[3] = {(float)rx * ir, (float)ry * ir, (float)rz * ir};
   // -j (cos kr - j sin kr) = -sin kr - j cos kr
-  const float f = (float)(k * eta / (4.0 * 3.14159265358979323846 * r));
+  const float f = ga.psi0 * ir;
   const float pr = -f * sn, pi = -f * cs;
-  const float ikr = (float)(1.0 / kr), ikr2 = ikr * ikr;
+  const float ikr = ir * ga.inv_k, ikr2 = ikr * ikr;
   const float iso_r = 1.f - ikr2, iso_i = -ikr;
   const float rr_r = 1.f - 3.f * ikr2, rr_i = -3.f * ikr;
   float vmax = 0.f;
@@ -688,7 +690,7 @@ __device__ void generate_operator(const GenArgs& ga, int o, unsigned short* img,
     const int dx = t / (SPAN * SPAN), dy = (t / SPAN) % SPAN, dz = t % SPAN;
     const double step = ga.a / ND;
     vmax = dyadic_green(ga.a * wx + step * (dx - (ND - 1)), ga.a * wy + step * (dy - (ND - 1)),
-                        ga.a * wz + step * (dz - (ND - 1)), ga.k, ga.eta, blk + 9 * t);
+                        ga.a * wz + step * (dz - (ND - 1)), ga, blk + 9 * t);
   }
   if (F16) {
 #pragma unroll
@@ -1672,7 +1674,8 @@ int launch_translate(const Plan& p, const float* P, float* part, int nrhs,
     const dim3 rgrid((unsigned)p.n_round_groups(), nrhs);
     if (p.gen_ops && (sk == kSplitRounds || sk == kSplitRoundsDouble))
       return (int)hipErrorInvalidValue;  // rejected by the schedule calls
-    const GenArgs ga{p.d_offsets, p.a, p.k, p.eta};
+    const GenArgs ga{p.d_offsets, p.a, p.k, (float)(1.0 / p.k),
+                     (float)(p.k * p.eta / (4.0 * 3.14159265358979323846))};
 #define UBF_SPLIT_CHUNKS(NU, F16, NPROD, WALK)                                                 \
   do {                                                                                         \
     if (p.gen_ops)                                                                             \
