@@ -49,10 +49,12 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E peak
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_04684_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_mvm_shell3338_hbm_traffic.json")
-# Stage events are recorded on one product in this many inside the timed
-# loop: an event costs a few microseconds of device time, about a tenth
-# of a product when all four are recorded on every product.
+# Stage times come from a loop of their own after the timed one (at least
+# PROFILE_CALLS products, --steps if larger), with the kernels' own dispatch
+# recording start and stop on one product in PROFILE_EVERY: a recorded
+# product takes about 14 us longer, so recording stays out of the timed loop.
 PROFILE_EVERY = 8
+PROFILE_CALLS = 200
 # Calls of each latency loop (at least; --steps if larger).
 LATENCY_CALLS = 200
 NETWORK_FILE = os.path.join(ROOT, "paper_2501_04684_amd", "data", "networks_nd4_h50_a0.125.npz")
@@ -307,15 +309,13 @@ def bench_networks(args, U, W, torch):
         for s in range(args.warmup):
             U.far_mvm(ff.plan, X[s % n_vec], Y, 1, stream)
         torch.cuda.synchronize()
-        n_rec = -(-args.steps // PROFILE_EVERY)
-        U.profile_begin(ff.plan, n_rec, PROFILE_EVERY)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(args.steps):
             U.far_mvm(ff.plan, X[s % n_vec], Y, 1, stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        stage_ms, call_ms = U.profile_end(ff.plan, n_rec)
+        stage_ms, call_ms = profiled_loop(U, torch, ff.plan, X, Y, 1, stream,
+                                          max(PROFILE_CALLS, args.steps))
         lat = latency_loops(U, torch, ff.plan, X, Y, 1, stream, max(LATENCY_CALLS, args.steps))
         U.far_mvm(ff.plan, X[0], Y, 1, stream)
         torch.cuda.synchronize()
@@ -471,15 +471,13 @@ def run_form(U, W, torch, w, precision, basis, nrhs, warmup, steps, copy_mb=0,
         U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
     torch.cuda.synchronize()
 
-    n_rec = -(-steps // PROFILE_EVERY)
-    U.profile_begin(ff.plan, n_rec, PROFILE_EVERY)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
         U.far_mvm(ff.plan, X[s % n_vec], Y, nrhs, stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stage_ms, call_ms = U.profile_end(ff.plan, n_rec)
+    stage_ms, call_ms = profiled_loop(U, torch, ff.plan, X, Y, nrhs, stream,
+                                      max(PROFILE_CALLS, steps))
 
     lat = latency_loops(U, torch, ff.plan, X, Y, nrhs, stream, max(LATENCY_CALLS, steps))
 
@@ -533,6 +531,19 @@ def tune_with_report(ff, nrhs, reps):
         if own:
             del os.environ["UBF_TUNE_CACHE"]
             os.remove(path)
+
+
+def profiled_loop(U, torch, plan, X, Y, nrhs, stream, n_calls):
+    """Per-stage kernel times (ms summed over the recorded products) and the
+    recorded products' times: n_calls products over the inputs X in turn,
+    one in PROFILE_EVERY recorded."""
+    n_rec = -(-n_calls // PROFILE_EVERY)
+    U.profile_begin(plan, n_rec, PROFILE_EVERY)
+    torch.cuda.synchronize()
+    for s in range(n_calls):
+        U.far_mvm(plan, X[s % len(X)], Y, nrhs, stream)
+    torch.cuda.synchronize()
+    return U.profile_end(plan, n_rec)
 
 
 def latency_loops(U, torch, plan, X, Y, nrhs, stream, n_calls):
