@@ -302,243 +302,6 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(
 
 // ---------------------------------------------------------------- stage 2
 
-// Matrix-core translation. A chunk is up to 128 box pairs sharing one
-// offset w; each workgroup walks a contiguous range of chunks (grouped by
-// offset, so consecutive chunks mostly reuse the operator already staged).
-// The complex product E = G_w P is done as the real product
-//   [Er; Ei] = [[Gr, -Gi], [Gi, Gr]] [Pr; Pi]
-// on v_mfma_f32_32x32x2_f32: M = 2*NU output rows in 32-row blocks,
-// K = 2*NU. Each wavefront owns 32 pair columns. Lane l holds column
-// l % 32 and K half h = l / 32 (h = 0: the Pr terms, h = 1: the Pi terms),
-// so a k-step of the MFMA pairs k = ks (h = 0) with k = NU + ks (h = 1) and
-// each lane's B values are one contiguous run of its box vector, kept in
-// registers. G_w sits in LDS as its two planes (rows of PITCH floats);
-// a lane reads the A values of four consecutive k-steps with one 16-byte
-// LDS read, negating -Gi with a sign flip.
-template <int NU>
-__global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
-    const float* __restrict__ table, const int32_t* __restrict__ chunks,
-    const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
-    const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
-    float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row) {
-  constexpr int KH = (NU + 3) & ~3;      // padded half-length, = PITCH
-  constexpr int PLANE = NU * KH;
-  constexpr int M = 2 * NU;
-  // Full 32-row blocks run on the matrix cores; up to 4 leftover rows (2 for
-  // N_u = 81: rows 160, 161) are accumulated on the VALU instead of a
-  // mostly empty extra block. Larger remainders take a padded block.
-  constexpr int LRV = (M % 32 <= 4) ? M % 32 : 0;   // VALU rows
-  constexpr int RB = (M - LRV + 31) / 32;            // MFMA row blocks
-  constexpr int NG = NU / 4;             // full groups of 4 k-steps
-  constexpr int PSTR = 2 * KH;
-  constexpr int N4 = 2 * PLANE / 4;      // float4s per operator
-  constexpr int LD = (N4 + kBlock - 1) / kBlock;
-  constexpr int NB4 = NU / 4;            // float4 loads of a lane's B run
-  __shared__ float4 lds4[N4];
-  const float* lds = reinterpret_cast<const float*>(lds4);
-
-  const int group = xcd_chunk(blockIdx.x, gridDim.x);
-  const int cbeg = wg_ptr[group], cend = wg_ptr[group + 1];
-  const int rhs = blockIdx.y;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = lane & 31, h = lane >> 5;
-
-  // Operator addressing: output row `row` of block rb for this lane.
-  // Er rows (< NU) read Gr for h = 0 and -Gi for h = 1; Ei rows read Gi for
-  // h = 0 and Gr for h = 1; padding rows (>= M) read row 0 (discarded).
-  int abase[RB + LRV];
-  unsigned asgn[RB + LRV];
-#pragma unroll
-  for (int rb = 0; rb < RB + LRV; ++rb) {
-    // MFMA blocks: this lane's row of block rb; VALU rows: row 32*RB + i.
-    const int row = rb < RB ? rb * 32 + r : 32 * RB + (rb - RB);
-    const bool er = row < NU;
-    const int rr = er ? row : (row < M ? row - NU : 0);
-    const bool im_plane = er ? (h == 1) : (row < M && h == 0);
-    abase[rb] = (im_plane ? PLANE : 0) + rr * KH;
-    asgn[rb] = (er && h == 1) ? 0x80000000u : 0u;
-  }
-
-  if (cbeg >= cend) return;
-  const int col0 = wave * 32;
-  const int64_t last = n_pairs - 1;
-
-  // Every global access below is unconditional, so the in-order counter of
-  // outstanding vector memory operations stays exact and waits are only as
-  // deep as needed: a lane past its chunk's count reads the column of a
-  // clamped (valid) pair and stores into the spare row `trash_row`; a B
-  // column only feeds its own output column, so nothing else is affected.
-  // Pair indices are fetched two chunks ahead (before the stores that lie
-  // between), B values one chunk ahead: while k-group g of the current
-  // chunk is multiplied, b's group g is refilled for the next chunk.
-  int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
-  const bool has1 = cbeg + 1 < cend;
-  int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
-  int b1 = has1 ? chunks[4 * (cbeg + 1) + 1] : 0;
-  int n1 = has1 ? chunks[4 * (cbeg + 1) + 2] : 0;
-  int64_t i0 = min((int64_t)b0 + col0 + r, last), i1 = min((int64_t)b1 + col0 + r, last);
-  int src0 = pair_src[i0], dst0 = pair_dst[i0];
-  int src1 = pair_src[i1], dst1 = pair_dst[i1];
-
-  float b[NU];
-  {
-    const float* pb = P + ((int64_t)rhs * n_box + src0) * PSTR + h * KH;
-#pragma unroll
-    for (int i = 0; i < NB4; ++i) {
-      const floatx4 v = reinterpret_cast<const floatx4*>(pb)[i];
-      b[4 * i] = v[0];
-      b[4 * i + 1] = v[1];
-      b[4 * i + 2] = v[2];
-      b[4 * i + 3] = v[3];
-    }
-#pragma unroll
-    for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb[ks];
-  }
-
-  int staged = -1;
-  for (int ch = cbeg; ch < cend; ++ch) {
-    if (o0 != staged) {  // uniform across the workgroup
-      __syncthreads();
-      const floatx4* g4 = reinterpret_cast<const floatx4*>(table + (size_t)o0 * 2 * PLANE);
-      floatx4* l4 = reinterpret_cast<floatx4*>(lds4);
-      floatx4 tmp[LD];  // every load in flight before the first LDS store
-#pragma unroll
-      for (int it = 0; it < LD; ++it) tmp[it] = g4[min((int)threadIdx.x + it * kBlock, N4 - 1)];
-#pragma unroll
-      for (int it = 0; it < LD; ++it) {
-        const int i = threadIdx.x + it * kBlock;
-        if (i < N4) l4[i] = tmp[it];
-      }
-      __syncthreads();
-      staged = o0;
-    }
-    const bool has2 = ch + 2 < cend;
-    const int o2 = has2 ? chunks[4 * (ch + 2)] : o1;
-    const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
-    const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
-    const int64_t i2 = min((int64_t)b2 + col0 + r, last);
-    const float* pb1 = P + ((int64_t)rhs * n_box + src1) * PSTR + h * KH;
-    int src2, dst2;
-
-    if (col0 < n0) {  // wave-uniform
-      floatx16 acc[RB];
-      float vacc[LRV > 0 ? LRV : 1];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
-#pragma unroll
-      for (int i = 0; i < LRV; ++i) vacc[i] = 0.f;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        float4 a[RB + LRV];
-#pragma unroll
-        for (int rb = 0; rb < RB + LRV; ++rb) {
-          const float4 v = *reinterpret_cast<const float4*>(lds + abase[rb] + 4 * g);
-          a[rb] = make_float4(__uint_as_float(__float_as_uint(v.x) ^ asgn[rb]),
-                              __uint_as_float(__float_as_uint(v.y) ^ asgn[rb]),
-                              __uint_as_float(__float_as_uint(v.z) ^ asgn[rb]),
-                              __uint_as_float(__float_as_uint(v.w) ^ asgn[rb]));
-        }
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb][jj], b[4 * g + jj], acc[rb], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < LRV; ++i) {
-          vacc[i] = fmaf(a[RB + i].x, b[4 * g], vacc[i]);
-          vacc[i] = fmaf(a[RB + i].y, b[4 * g + 1], vacc[i]);
-          vacc[i] = fmaf(a[RB + i].z, b[4 * g + 2], vacc[i]);
-          vacc[i] = fmaf(a[RB + i].w, b[4 * g + 3], vacc[i]);
-        }
-        const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[g];  // next chunk
-        b[4 * g] = v[0];
-        b[4 * g + 1] = v[1];
-        b[4 * g + 2] = v[2];
-        b[4 * g + 3] = v[3];
-      }
-#pragma unroll
-      for (int ks = 4 * NG; ks < NU; ++ks) {
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const float av = __uint_as_float(__float_as_uint(lds[abase[rb] + ks]) ^ asgn[rb]);
-          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[ks], acc[rb], 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < LRV; ++i) {
-          const float av = __uint_as_float(__float_as_uint(lds[abase[RB + i] + ks]) ^ asgn[RB + i]);
-          vacc[i] = fmaf(av, b[ks], vacc[i]);
-        }
-        b[ks] = pb1[ks];
-      }
-      // VALU rows: add the other K half (lane l +- 32 holds it).
-#pragma unroll
-      for (int i = 0; i < LRV; ++i) vacc[i] += __shfl_xor(vacc[i], 32, 64);
-      src2 = pair_src[i2];
-      dst2 = pair_dst[i2];
-
-      // D layout of a 32x32 block: lane l holds column l % 32, rows
-      // 8*(v/4) + 4*(l/32) + v%4 in accumulator element v.
-      const int64_t row = (col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
-      float* out = part + row * PSTR;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          const int r0 = rb * 32 + 8 * q4 + 4 * h;
-          if (rb * 32 + 8 * q4 + 8 <= PSTR)  // same for both halves h
-            *reinterpret_cast<floatx4*>(out + r0) =
-                floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
-                        acc[rb][4 * q4 + 3]};
-        }
-      if (LRV > 0) {
-        // rows 32*RB .. 32*RB+LRV-1; lanes of both halves hold the sums,
-        // half h writes the even/odd pair starting at 2*h
-#pragma unroll
-        for (int i = 0; i < LRV; i += 2) {
-          if (i + 1 < LRV) {
-            if (2 * h == i % 4)
-              *reinterpret_cast<float2*>(out + 32 * RB + i) = make_float2(vacc[i], vacc[i + 1]);
-          } else if (h == 0) {
-            out[32 * RB + i] = vacc[i];
-          }
-        }
-      }
-    } else {  // no column of this chunk for this wavefront: fetch the next
-#pragma unroll
-      for (int i = 0; i < NB4; ++i) {
-        const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[i];
-        b[4 * i] = v[0];
-        b[4 * i + 1] = v[1];
-        b[4 * i + 2] = v[2];
-        b[4 * i + 3] = v[3];
-      }
-#pragma unroll
-      for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb1[ks];
-      src2 = pair_src[i2];
-      dst2 = pair_dst[i2];
-    }
-    o0 = o1; n0 = n1; dst0 = dst1;
-    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;
-  }
-}
-
-template <bool F16>
-struct Mfma16;
-template <>
-struct Mfma16<false> {
-  typedef bf16x8 vec;
-  static __device__ inline floatx16 run(vec a, vec b, floatx16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct Mfma16<true> {
-  typedef halfx8 vec;
-  static __device__ inline floatx16 run(vec a, vec b, floatx16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-  }
-};
-
 // Waits until at most N vector-memory operations of this wavefront are
 // outstanding (vmcnt; expcnt and lgkmcnt left unconstrained).
 template <int N>
@@ -579,6 +342,260 @@ __device__ inline void copy_to_lds(const uintx4* __restrict__ src, uintx4* dst) 
         reinterpret_cast<const void*>(src + min(t + it * kBlock, N16 - 1)),
         (__attribute__((address_space(3))) void*)(dst + it * kBlock + wave * 64), 16, 0, 0);
 }
+
+// Matrix-core translation. A chunk is up to 128 box pairs sharing one
+// offset w; each workgroup walks a contiguous range of chunks (grouped by
+// offset, so consecutive chunks mostly reuse the operator already staged).
+// The complex product E = G_w P is done as the real product
+//   [Er; Ei] = [[Gr, -Gi], [Gi, Gr]] [Pr; Pi]
+// on v_mfma_f32_32x32x2_f32: M = 2*NU output rows in 32-row blocks,
+// K = 2*NU. Each wavefront owns 32 pair columns. Lane l holds column
+// l % 32 and K half h = l / 32 (h = 0: the Pr terms, h = 1: the Pi terms),
+// so a k-step of the MFMA pairs k = ks (h = 0) with k = NU + ks (h = 1) and
+// each lane's B values are one contiguous run of its box vector, kept in
+// registers. G_w sits in LDS as its two planes (rows of PITCH floats);
+// a lane reads the A values of four consecutive k-steps with one 16-byte
+// LDS read, negating -Gi with a sign flip. Operators are copied global ->
+// LDS directly: the first before the loop, each later one (when the next
+// chunk has another offset) after every wavefront's last products and
+// before the partial rows leave, so that the copy and the stores are in
+// flight together; the next chunk waits for the copy alone.
+template <int NU>
+__device__ constexpr int fp32_row_stores() {
+  constexpr int KH = (NU + 3) & ~3, M = 2 * NU, PSTR = 2 * KH;
+  constexpr int LRV = (M % 32 <= 4) ? M % 32 : 0;
+  constexpr int RB = (M - LRV + 31) / 32;
+  int n = 0;
+  for (int rb = 0; rb < RB; ++rb)
+    for (int q4 = 0; q4 < 4; ++q4)
+      if (rb * 32 + 8 * q4 + 8 <= PSTR) ++n;
+  return n + (LRV + 1) / 2;
+}
+
+template <int NU>
+__global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
+    const float* __restrict__ table, const int32_t* __restrict__ chunks,
+    const int32_t* __restrict__ wg_ptr, const int32_t* __restrict__ pair_src,
+    const int32_t* __restrict__ pair_dst, const float* __restrict__ P,
+    float* __restrict__ part, int64_t n_box, int64_t n_pairs, int64_t trash_row) {
+  constexpr int KH = (NU + 3) & ~3;      // padded half-length, = PITCH
+  constexpr int PLANE = NU * KH;
+  constexpr int M = 2 * NU;
+  // Full 32-row blocks run on the matrix cores; up to 4 leftover rows (2 for
+  // N_u = 81: rows 160, 161) are accumulated on the VALU instead of a
+  // mostly empty extra block. Larger remainders take a padded block.
+  constexpr int LRV = (M % 32 <= 4) ? M % 32 : 0;   // VALU rows
+  constexpr int RB = (M - LRV + 31) / 32;            // MFMA row blocks
+  constexpr int NG = NU / 4;             // full groups of 4 k-steps
+  constexpr int PSTR = 2 * KH;
+  constexpr int N4 = 2 * PLANE / 4;      // 16-byte units per operator
+  constexpr int HP = (N4 + kBlock - 1) / kBlock * kBlock;  // LDS units
+  constexpr int NB4 = NU / 4;            // float4 loads of a lane's B run
+  constexpr int NST = fp32_row_stores<NU>();  // stores per wavefront and chunk
+  __shared__ uintx4 lds4[HP];
+  const float* lds = reinterpret_cast<const float*>(lds4);
+
+  const int group = xcd_chunk(blockIdx.x, gridDim.x);
+  const int cbeg = wg_ptr[group], cend = wg_ptr[group + 1];
+  const int rhs = blockIdx.y;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int r = lane & 31, h = lane >> 5;
+
+  // Operator addressing: output row `row` of block rb for this lane.
+  // Er rows (< NU) read Gr for h = 0 and -Gi for h = 1; Ei rows read Gi for
+  // h = 0 and Gr for h = 1; padding rows (>= M) read row 0 (discarded).
+  int abase[RB + LRV];
+  unsigned asgn[RB + LRV];
+#pragma unroll
+  for (int rb = 0; rb < RB + LRV; ++rb) {
+    // MFMA blocks: this lane's row of block rb; VALU rows: row 32*RB + i.
+    const int row = rb < RB ? rb * 32 + r : 32 * RB + (rb - RB);
+    const bool er = row < NU;
+    const int rr = er ? row : (row < M ? row - NU : 0);
+    const bool im_plane = er ? (h == 1) : (row < M && h == 0);
+    abase[rb] = (im_plane ? PLANE : 0) + rr * KH;
+    asgn[rb] = (er && h == 1) ? 0x80000000u : 0u;
+  }
+
+  if (cbeg >= cend) return;
+  const int col0 = wave * 32;
+  const int64_t last = n_pairs - 1;
+
+  // Every global access below is unconditional, so the in-order counter of
+  // outstanding vector memory operations stays exact and waits are only as
+  // deep as needed: a lane past its chunk's count (or a wavefront past it)
+  // reads the column of a clamped (valid) pair and stores into the spare
+  // row `trash_row`; a B column only feeds its own output column, so nothing
+  // else is affected. Pair indices are fetched two chunks ahead (before the
+  // stores that lie between), B values one chunk ahead: while k-group g of
+  // the current chunk is multiplied, b's group g is refilled for the next.
+  int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
+  const bool has1 = cbeg + 1 < cend;
+  int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
+  int b1 = has1 ? chunks[4 * (cbeg + 1) + 1] : 0;
+  int n1 = has1 ? chunks[4 * (cbeg + 1) + 2] : 0;
+  int64_t i0 = min((int64_t)b0 + col0 + r, last), i1 = min((int64_t)b1 + col0 + r, last);
+  int src0 = pair_src[i0], dst0 = pair_dst[i0];
+  int src1 = pair_src[i1], dst1 = pair_dst[i1];
+
+  float b[NU];
+  {
+    const float* pb = P + ((int64_t)rhs * n_box + src0) * PSTR + h * KH;
+#pragma unroll
+    for (int i = 0; i < NB4; ++i) {
+      const floatx4 v = reinterpret_cast<const floatx4*>(pb)[i];
+      b[4 * i] = v[0];
+      b[4 * i + 1] = v[1];
+      b[4 * i + 2] = v[2];
+      b[4 * i + 3] = v[3];
+    }
+#pragma unroll
+    for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb[ks];
+  }
+  const uintx4* gt = reinterpret_cast<const uintx4*>(table);
+  copy_to_lds<N4>(gt + (size_t)o0 * N4, lds4);
+  wait_vmcnt<0>();
+  lds_copies_done_barrier();
+
+  bool pending = false;
+  for (int ch = cbeg; ch < cend; ++ch) {
+    // the copy (if any), the column refills and the indices were issued
+    // just before the previous chunk's NST stores; waiting here whether or
+    // not a copy is pending lets the compiler see that none is
+    wait_vmcnt<NST>();
+    if (pending) {
+      lds_copies_done_barrier();
+      pending = false;
+    }
+    const bool has2 = ch + 2 < cend;
+    const int o2 = has2 ? chunks[4 * (ch + 2)] : o1;
+    const int b2 = has2 ? chunks[4 * (ch + 2) + 1] : 0;
+    const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
+    const int64_t i2 = min((int64_t)b2 + col0 + r, last);
+    const float* pb1 = P + ((int64_t)rhs * n_box + src1) * PSTR + h * KH;
+    const bool active = col0 < n0;  // wave-uniform
+    // pair indices two chunks ahead: requested before the refills, so that
+    // taking them into registers before the copy below waits for them alone
+    int src2 = pair_src[i2];
+    int dst2 = pair_dst[i2];
+
+    floatx16 acc[RB];
+    float vacc[LRV > 0 ? LRV : 1];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+#pragma unroll
+    for (int i = 0; i < LRV; ++i) vacc[i] = 0.f;
+    // (the test is per k-group so that each refill stays next to its
+    // k-group's products)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      if (active) {
+        float4 a[RB + LRV];
+#pragma unroll
+        for (int rb = 0; rb < RB + LRV; ++rb) {
+          const float4 v = *reinterpret_cast<const float4*>(lds + abase[rb] + 4 * g);
+          a[rb] = make_float4(__uint_as_float(__float_as_uint(v.x) ^ asgn[rb]),
+                              __uint_as_float(__float_as_uint(v.y) ^ asgn[rb]),
+                              __uint_as_float(__float_as_uint(v.z) ^ asgn[rb]),
+                              __uint_as_float(__float_as_uint(v.w) ^ asgn[rb]));
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb][jj], b[4 * g + jj], acc[rb], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < LRV; ++i) {
+          vacc[i] = fmaf(a[RB + i].x, b[4 * g], vacc[i]);
+          vacc[i] = fmaf(a[RB + i].y, b[4 * g + 1], vacc[i]);
+          vacc[i] = fmaf(a[RB + i].z, b[4 * g + 2], vacc[i]);
+          vacc[i] = fmaf(a[RB + i].w, b[4 * g + 3], vacc[i]);
+        }
+      }
+      const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[g];  // next chunk
+      b[4 * g] = v[0];
+      b[4 * g + 1] = v[1];
+      b[4 * g + 2] = v[2];
+      b[4 * g + 3] = v[3];
+    }
+#pragma unroll
+    for (int ks = 4 * NG; ks < NU; ++ks) {
+      if (active) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const float av = __uint_as_float(__float_as_uint(lds[abase[rb] + ks]) ^ asgn[rb]);
+          acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[ks], acc[rb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < LRV; ++i) {
+          const float av = __uint_as_float(__float_as_uint(lds[abase[RB + i] + ks]) ^ asgn[RB + i]);
+          vacc[i] = fmaf(av, b[ks], vacc[i]);
+        }
+      }
+      b[ks] = pb1[ks];
+    }
+    // VALU rows: add the other K half (lane l +- 32 holds it).
+#pragma unroll
+    for (int i = 0; i < LRV; ++i) vacc[i] += __shfl_xor(vacc[i], 32, 64);
+    // Taken into registers here, before a direct copy into LDS may be in
+    // flight: the compiler makes any wait for a loaded register issued
+    // behind such a copy wait for all memory operations.
+    asm volatile("" : "+v"(src2), "+v"(dst2));
+    if (ch + 1 < cend && o1 != o0) {  // uniform: the next chunk has another operator
+      lds_reads_done_barrier();
+      copy_to_lds<N4>(gt + (size_t)o1 * N4, lds4);
+      pending = true;
+    }
+
+    // D layout of a 32x32 block: lane l holds column l % 32, rows
+    // 8*(v/4) + 4*(l/32) + v%4 in accumulator element v. Every wavefront
+    // stores NST times (absent columns go to the spare row), which the
+    // wait for the copy above counts on.
+    const int64_t row = (active && col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
+    float* out = part + row * PSTR;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int r0 = rb * 32 + 8 * q4 + 4 * h;
+        if (rb * 32 + 8 * q4 + 8 <= PSTR)  // same for both halves h
+          *reinterpret_cast<floatx4*>(out + r0) =
+              floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                      acc[rb][4 * q4 + 3]};
+      }
+    if (LRV > 0) {
+      // rows 32*RB .. 32*RB+LRV-1: lanes of both halves hold the same sums
+      // and both write them (same values to the same place), so that the
+      // stores are not under a lane test
+#pragma unroll
+      for (int i = 0; i < LRV; i += 2) {
+        if (i + 1 < LRV)
+          *reinterpret_cast<float2*>(out + 32 * RB + i) = make_float2(vacc[i], vacc[i + 1]);
+        else
+          out[32 * RB + i] = vacc[i];
+      }
+    }
+    o0 = o1; n0 = n1; dst0 = dst1;
+    o1 = o2; n1 = n2; src1 = src2; dst1 = dst2;
+  }
+}
+
+template <bool F16>
+struct Mfma16;
+template <>
+struct Mfma16<false> {
+  typedef bf16x8 vec;
+  static __device__ inline floatx16 run(vec a, vec b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16<true> {
+  typedef halfx8 vec;
+  static __device__ inline floatx16 run(vec a, vec b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
 
 // 32-bit LDS address of a pointer into __shared__ memory.
 __device__ inline unsigned lds_address(const float* p) {
