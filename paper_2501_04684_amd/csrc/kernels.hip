@@ -894,16 +894,11 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
         generate_operator<NU, F16, NPROD>(ga, o0, img, LO, blk, gen_max, gen_scale);
         staged = o0;
       }
-    } else {
-      // the copy (if any) and the column refills were issued just before
-      // the previous unit's RB * 4 stores; waiting here whether or not a
-      // copy is pending lets the compiler see that none is (it would
-      // otherwise wait for the stores before the first products)
+    } else if (pending) {
+      // the copy was issued just before the previous unit's RB * 4 stores
       wait_vmcnt<RB * 4>();
-      if (pending) {
-        lds_copies_done_barrier();
-        pending = false;
-      }
+      lds_copies_done_barrier();
+      pending = false;
     }
     const bool has1 = v + 1 < vend;
     const int c1 = (v + 1) / nv;
@@ -913,7 +908,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     const int n1 = has1 ? chunks[4 * c1 + 2] : 0;
     const int64_t i1 = min((int64_t)b1 + col0 + r, last);
     const int src1 = pair_src[i1];
-    int dst1 = pair_dst[i1];
+    const int dst1 = pair_dst[i1];
     const bool active = col0 < n0;  // wave-uniform
 
     floatx16 acc[RB];
@@ -941,7 +936,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     // the next unit's column: its box vector is fetched in pass 2, its FP16
     // scale here
     const vec16* pv1 = reinterpret_cast<const vec16*>(P + ((int64_t)rhs1 * n_box + src1) * VSTR);
-    float bsc1 = F16 ? box_scale[(int64_t)rhs1 * n_box + src1] : 1.f;
+    const float bsc1 = F16 ? box_scale[(int64_t)rhs1 * n_box + src1] : 1.f;
     // pass 2: Gl Ph, refilling the registers with the next unit's columns
     // (the test is per k-step so that each refill stays next to its k-step's
     // products instead of being gathered after the pass)
@@ -963,11 +958,6 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
       }
       bh[g] = pv1[4 * g + h];
     }
-    // The next unit's destination row and scale are taken here, before a
-    // direct copy into LDS may be in flight: the compiler makes any wait for
-    // a loaded register issued behind such a copy wait for all memory
-    // operations, the partial-row stores included.
-    asm volatile("" : "+v"(dst1), "+v"(bsc1));
     if (!GEN && has1 && o1 != o0) {  // uniform: the next unit has another operator
       lds_reads_done_barrier();
       copy_to_lds<H16>(gt + (size_t)o1 * OPU, lds4);
