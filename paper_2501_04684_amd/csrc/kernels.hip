@@ -358,20 +358,8 @@ __device__ inline void copy_to_lds(const uintx4* __restrict__ src, uintx4* dst) 
 // LDS read, negating -Gi with a sign flip. Operators are copied global ->
 // LDS directly: the first before the loop, each later one (when the next
 // chunk has another offset) after every wavefront's last products and
-// before the partial rows leave, so that the copy and the stores are in
-// flight together; the next chunk waits for the copy alone.
-template <int NU>
-__device__ constexpr int fp32_row_stores() {
-  constexpr int KH = (NU + 3) & ~3, M = 2 * NU, PSTR = 2 * KH;
-  constexpr int LRV = (M % 32 <= 4) ? M % 32 : 0;
-  constexpr int RB = (M - LRV + 31) / 32;
-  int n = 0;
-  for (int rb = 0; rb < RB; ++rb)
-    for (int q4 = 0; q4 < 4; ++q4)
-      if (rb * 32 + 8 * q4 + 8 <= PSTR) ++n;
-  return n + (LRV + 1) / 2;
-}
-
+// before the partial rows leave, so that the copy is in flight with the
+// stores; the next chunk then waits for both.
 template <int NU>
 __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
     const float* __restrict__ table, const int32_t* __restrict__ chunks,
@@ -391,14 +379,13 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
   constexpr int N4 = 2 * PLANE / 4;      // 16-byte units per operator
   constexpr int HP = (N4 + kBlock - 1) / kBlock * kBlock;  // LDS units
   constexpr int NB4 = NU / 4;            // float4 loads of a lane's B run
-  constexpr int NST = fp32_row_stores<NU>();  // stores per wavefront and chunk
   __shared__ uintx4 lds4[HP];
   const float* lds = reinterpret_cast<const float*>(lds4);
 
   const int group = xcd_chunk(blockIdx.x, gridDim.x);
   const int cbeg = wg_ptr[group], cend = wg_ptr[group + 1];
   const int rhs = blockIdx.y;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 31, h = lane >> 5;
 
   // Operator addressing: output row `row` of block rb for this lane.
@@ -423,12 +410,12 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
 
   // Every global access below is unconditional, so the in-order counter of
   // outstanding vector memory operations stays exact and waits are only as
-  // deep as needed: a lane past its chunk's count (or a wavefront past it)
-  // reads the column of a clamped (valid) pair and stores into the spare
-  // row `trash_row`; a B column only feeds its own output column, so nothing
-  // else is affected. Pair indices are fetched two chunks ahead (before the
-  // stores that lie between), B values one chunk ahead: while k-group g of
-  // the current chunk is multiplied, b's group g is refilled for the next.
+  // deep as needed: a lane past its chunk's count reads the column of a
+  // clamped (valid) pair and stores into the spare row `trash_row`; a B
+  // column only feeds its own output column, so nothing else is affected.
+  // Pair indices are fetched two chunks ahead (before the stores that lie
+  // between), B values one chunk ahead: while k-group g of the current
+  // chunk is multiplied, b's group g is refilled for the next chunk.
   int o0 = chunks[4 * cbeg], b0 = chunks[4 * cbeg + 1], n0 = chunks[4 * cbeg + 2];
   const bool has1 = cbeg + 1 < cend;
   int o1 = has1 ? chunks[4 * (cbeg + 1)] : o0;
@@ -452,18 +439,15 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
 #pragma unroll
     for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb[ks];
   }
+
   const uintx4* gt = reinterpret_cast<const uintx4*>(table);
   copy_to_lds<N4>(gt + (size_t)o0 * N4, lds4);
   wait_vmcnt<0>();
   lds_copies_done_barrier();
-
   bool pending = false;
   for (int ch = cbeg; ch < cend; ++ch) {
-    // the copy (if any), the column refills and the indices were issued
-    // just before the previous chunk's NST stores; waiting here whether or
-    // not a copy is pending lets the compiler see that none is
-    wait_vmcnt<NST>();
-    if (pending) {
+    if (pending) {  // uniform: the copy issued during the previous chunk
+      wait_vmcnt<0>();
       lds_copies_done_barrier();
       pending = false;
     }
@@ -473,23 +457,18 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
     const int n2 = has2 ? chunks[4 * (ch + 2) + 2] : 0;
     const int64_t i2 = min((int64_t)b2 + col0 + r, last);
     const float* pb1 = P + ((int64_t)rhs * n_box + src1) * PSTR + h * KH;
-    const bool active = col0 < n0;  // wave-uniform
-    // pair indices two chunks ahead: requested before the refills, so that
-    // taking them into registers before the copy below waits for them alone
-    int src2 = pair_src[i2];
-    int dst2 = pair_dst[i2];
+    int src2, dst2;
 
+    const bool active = col0 < n0;  // wave-uniform
     floatx16 acc[RB];
     float vacc[LRV > 0 ? LRV : 1];
+    if (active) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
 #pragma unroll
-    for (int i = 0; i < LRV; ++i) vacc[i] = 0.f;
-    // (the test is per k-group so that each refill stays next to its
-    // k-group's products)
+      for (int i = 0; i < LRV; ++i) vacc[i] = 0.f;
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      if (active) {
+      for (int g = 0; g < NG; ++g) {
         float4 a[RB + LRV];
 #pragma unroll
         for (int rb = 0; rb < RB + LRV; ++rb) {
@@ -511,16 +490,14 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
           vacc[i] = fmaf(a[RB + i].z, b[4 * g + 2], vacc[i]);
           vacc[i] = fmaf(a[RB + i].w, b[4 * g + 3], vacc[i]);
         }
+        const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[g];  // next chunk
+        b[4 * g] = v[0];
+        b[4 * g + 1] = v[1];
+        b[4 * g + 2] = v[2];
+        b[4 * g + 3] = v[3];
       }
-      const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[g];  // next chunk
-      b[4 * g] = v[0];
-      b[4 * g + 1] = v[1];
-      b[4 * g + 2] = v[2];
-      b[4 * g + 3] = v[3];
-    }
 #pragma unroll
-    for (int ks = 4 * NG; ks < NU; ++ks) {
-      if (active) {
+      for (int ks = 4 * NG; ks < NU; ++ks) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           const float av = __uint_as_float(__float_as_uint(lds[abase[rb] + ks]) ^ asgn[rb]);
@@ -531,48 +508,61 @@ __global__ __launch_bounds__(kBlock, 2) void translate_mfma_kernel(
           const float av = __uint_as_float(__float_as_uint(lds[abase[RB + i] + ks]) ^ asgn[RB + i]);
           vacc[i] = fmaf(av, b[ks], vacc[i]);
         }
+        b[ks] = pb1[ks];
       }
-      b[ks] = pb1[ks];
-    }
-    // VALU rows: add the other K half (lane l +- 32 holds it).
+      // VALU rows: add the other K half (lane l +- 32 holds it).
 #pragma unroll
-    for (int i = 0; i < LRV; ++i) vacc[i] += __shfl_xor(vacc[i], 32, 64);
-    // Taken into registers here, before a direct copy into LDS may be in
-    // flight: the compiler makes any wait for a loaded register issued
-    // behind such a copy wait for all memory operations.
-    asm volatile("" : "+v"(src2), "+v"(dst2));
+      for (int i = 0; i < LRV; ++i) vacc[i] += __shfl_xor(vacc[i], 32, 64);
+    } else {  // no column of this chunk for this wavefront: fetch the next
+#pragma unroll
+      for (int i = 0; i < NB4; ++i) {
+        const floatx4 v = reinterpret_cast<const floatx4*>(pb1)[i];
+        b[4 * i] = v[0];
+        b[4 * i + 1] = v[1];
+        b[4 * i + 2] = v[2];
+        b[4 * i + 3] = v[3];
+      }
+#pragma unroll
+      for (int ks = 4 * NB4; ks < NU; ++ks) b[ks] = pb1[ks];
+    }
+    src2 = pair_src[i2];
+    dst2 = pair_dst[i2];
     if (ch + 1 < cend && o1 != o0) {  // uniform: the next chunk has another operator
+      // the destination row is taken before the copy: a wait for a loaded
+      // register issued behind a direct copy into LDS waits for all memory
+      // operations
+      asm volatile("" : "+v"(dst0));
       lds_reads_done_barrier();
       copy_to_lds<N4>(gt + (size_t)o1 * N4, lds4);
       pending = true;
     }
-
-    // D layout of a 32x32 block: lane l holds column l % 32, rows
-    // 8*(v/4) + 4*(l/32) + v%4 in accumulator element v. Every wavefront
-    // stores NST times (absent columns go to the spare row), which the
-    // wait for the copy above counts on.
-    const int64_t row = (active && col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
-    float* out = part + row * PSTR;
+    if (active) {
+      // D layout of a 32x32 block: lane l holds column l % 32, rows
+      // 8*(v/4) + 4*(l/32) + v%4 in accumulator element v.
+      const int64_t row = (col0 + r < n0) ? (int64_t)rhs * n_pairs + dst0 : trash_row;
+      float* out = part + row * PSTR;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4) {
-        const int r0 = rb * 32 + 8 * q4 + 4 * h;
-        if (rb * 32 + 8 * q4 + 8 <= PSTR)  // same for both halves h
-          *reinterpret_cast<floatx4*>(out + r0) =
-              floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
-                      acc[rb][4 * q4 + 3]};
-      }
-    if (LRV > 0) {
-      // rows 32*RB .. 32*RB+LRV-1: lanes of both halves hold the same sums
-      // and both write them (same values to the same place), so that the
-      // stores are not under a lane test
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int r0 = rb * 32 + 8 * q4 + 4 * h;
+          if (rb * 32 + 8 * q4 + 8 <= PSTR)  // same for both halves h
+            *reinterpret_cast<floatx4*>(out + r0) =
+                floatx4{acc[rb][4 * q4], acc[rb][4 * q4 + 1], acc[rb][4 * q4 + 2],
+                        acc[rb][4 * q4 + 3]};
+        }
+      if (LRV > 0) {
+        // rows 32*RB .. 32*RB+LRV-1; lanes of both halves hold the sums,
+        // half h writes the even/odd pair starting at 2*h
 #pragma unroll
-      for (int i = 0; i < LRV; i += 2) {
-        if (i + 1 < LRV)
-          *reinterpret_cast<float2*>(out + 32 * RB + i) = make_float2(vacc[i], vacc[i + 1]);
-        else
-          out[32 * RB + i] = vacc[i];
+        for (int i = 0; i < LRV; i += 2) {
+          if (i + 1 < LRV) {
+            if (2 * h == i % 4)
+              *reinterpret_cast<float2*>(out + 32 * RB + i) = make_float2(vacc[i], vacc[i + 1]);
+          } else if (h == 0) {
+            out[32 * RB + i] = vacc[i];
+          }
+        }
       }
     }
     o0 = o1; n0 = n1; dst0 = dst1;
@@ -914,6 +904,10 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
     floatx16 acc[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx16{};
+    // The passes run at a raised wavefront priority: the other wavefront on
+    // the SIMD (another workgroup's) is then mostly in its copy, stores or
+    // start, and its instructions are issued around the matrix-core ones.
+    __builtin_amdgcn_s_setprio(1);
     if (active) {
       // pass 1: Gh Ph (+ Gh Pl)
 #pragma unroll
@@ -958,6 +952,7 @@ __global__ __launch_bounds__(kBlock, 2) void translate_split_kernel(
       }
       bh[g] = pv1[4 * g + h];
     }
+    __builtin_amdgcn_s_setprio(0);
     if (!GEN && has1 && o1 != o0) {  // uniform: the next unit has another operator
       lds_reads_done_barrier();
       copy_to_lds<H16>(gt + (size_t)o1 * OPU, lds4);
